@@ -1,0 +1,120 @@
+"""CPU oracle for dense-matrix single-source shortest paths (Algorithm 1 of the paper).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library.  The arithmetic
+lives in oracle.c (plain serial C, exact int64 sums); this file only marshals
+numpy arrays.  See oracle.c for the readings taken where the paper is silent
+(tie rule, pred initial value, infinity encoding, early exit).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+INF = 0x7FFFFFFF
+INF64 = 1 << 62
+_lib = None
+
+CERT_CODES = {
+    0: "ok",
+    1: "dist[src] != 0 or pred[src] != -1",
+    2: "infeasible edge: dist[u] + W[u][v] < dist[v]",
+    3: "pred edge of a reachable vertex is not tight",
+    4: "unreachable vertex with pred != -1",
+    5: "pred chain does not reach the source",
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        L.oracle_dijkstra.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                      ctypes.c_int32]
+        L.oracle_dijkstra.restype = ctypes.c_int64
+        L.oracle_floyd_warshall.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P]
+        L.oracle_floyd_warshall.restype = ctypes.c_int
+        L.oracle_bellman_ford.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
+        L.oracle_bellman_ford.restype = ctypes.c_int
+        L.oracle_certificate.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P,
+                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_certificate.restype = ctypes.c_int
+        L.oracle_closed_form_pred.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P,
+                                              ctypes.c_int32]
+        L.oracle_closed_form_pred.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _mat(W):
+    W = np.asarray(W)
+    if W.dtype != np.int32 or W.ndim != 2 or W.strides[1] != 4 or W.strides[0] % 4:
+        W = np.ascontiguousarray(W, dtype=np.int32)
+    return W, W.strides[0] // 4
+
+
+def _threads(t):
+    return t or max(1, min(16, os.cpu_count() or 1))
+
+
+def dijkstra(W, src, early_exit=True, with_order=False):
+    """Algorithm 1: returns (dist, pred[, order], relaxed_rows)."""
+    W, ld = _mat(W)
+    n = W.shape[0]
+    dist = np.empty(n, np.int32)
+    pred = np.empty(n, np.int32)
+    order = np.empty(n, np.int32) if with_order else None
+    r = lib().oracle_dijkstra(W.ctypes.data, ld, n, src, dist.ctypes.data, pred.ctypes.data,
+                              order.ctypes.data if with_order else None, int(bool(early_exit)))
+    if r < 0:
+        raise ValueError("oracle_dijkstra rejected the arguments")
+    if with_order:
+        return dist, pred, order, int(r)
+    return dist, pred, int(r)
+
+
+def floyd_warshall(W):
+    W, ld = _mat(W)
+    n = W.shape[0]
+    D = np.empty((n, n), np.int64)
+    if lib().oracle_floyd_warshall(W.ctypes.data, ld, n, D.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return D
+
+
+def bellman_ford(W, src):
+    W, ld = _mat(W)
+    n = W.shape[0]
+    d = np.empty(n, np.int64)
+    if lib().oracle_bellman_ford(W.ctypes.data, ld, n, src, d.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return d
+
+
+def certificate(W, src, dist, pred, threads=None):
+    """Returns (code, where); code 0 means (dist, pred) is a valid shortest-path tree."""
+    W, ld = _mat(W)
+    dist = np.ascontiguousarray(dist, np.int32)
+    pred = np.ascontiguousarray(pred, np.int32)
+    where = ctypes.c_int64(-1)
+    code = lib().oracle_certificate(W.ctypes.data, ld, W.shape[0], src, dist.ctypes.data,
+                                    pred.ctypes.data, _threads(threads), ctypes.byref(where))
+    if code < 0:
+        raise ValueError("bad arguments")
+    return code, int(where.value)
+
+
+def closed_form_pred(W, dist, threads=None):
+    W, ld = _mat(W)
+    dist = np.ascontiguousarray(dist, np.int32)
+    pred = np.empty(W.shape[0], np.int32)
+    if lib().oracle_closed_form_pred(W.ctypes.data, ld, W.shape[0], dist.ctypes.data,
+                                     pred.ctypes.data, _threads(threads)) != 0:
+        raise ValueError("bad arguments")
+    return pred
