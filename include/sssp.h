@@ -1,0 +1,127 @@
+/*
+ * sssp.h — C ABI of libsssp: single-source shortest paths on a dense n x n
+ * int32 adjacency matrix, by Dijkstra's algorithm as given in Algorithm 1 of
+ * "High-Performance Parallelization of Dijkstra's Algorithm Using MPI and CUDA"
+ * (Section III-A), on AMD Instinct MI355X (gfx950).
+ *
+ * Data conventions (Section III-A's adjacency matrix):
+ *   W      device pointer, row-major int32, n rows of `ld` entries (ld >= n).
+ *          W[u*ld + v] is the weight of edge u -> v; INT32_MAX means "no edge"
+ *          (the paper's infinity); the diagonal should be 0.  Weights must lie
+ *          in [0, INT32_MAX-1]; a negative weight violates the precondition of
+ *          Dijkstra's algorithm (its result is then unspecified; the kernels
+ *          raise SSSP_STATUS_NEG_WEIGHT when they notice one).
+ *   dist   device pointer, n int32 outputs: shortest distance from src, or
+ *          INT32_MAX when unreachable.
+ *   pred   device pointer, n int32 outputs: predecessor on the shortest path
+ *          that Algorithm 1 finds (argmin ties go to the lowest vertex index,
+ *          relaxation uses a strict '<'); -1 for src and unreachable vertices.
+ * All buffers belong to the caller and must stay valid until the work that
+ * uses them has finished on the stream.  The library owns only its internal
+ * scratch (barrier words, exchange records), cached per (device, stream).
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Solves are
+ * asynchronous; synchronise the stream before reading dist/pred.  Calls that
+ * share a stream are ordered; solves issued on different streams use separate
+ * scratch and may overlap.
+ *
+ * Errors: every entry point returns SSSP_OK (0) or a negative SSSP_E* code and
+ * never throws.  sssp_last_error() returns a message for the calling thread's
+ * most recent failure.  Faults detected inside a kernel (a barrier that timed
+ * out, a negative weight) are reported asynchronously through
+ * sssp_last_status().
+ */
+#ifndef SSSP_H
+#define SSSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SSSP_OK 0
+#define SSSP_EINVAL (-1)     /* bad argument: null pointer, n < 1, src outside [0, n), ld < n, ... */
+#define SSSP_EDEVICE (-2)    /* a HIP runtime call failed */
+#define SSSP_ENOMEM (-3)     /* scratch allocation failed */
+#define SSSP_EAGAIN (-4)     /* server admission full; retry later */
+#define SSSP_ENOGRAPH (-5)   /* unknown server graph id */
+#define SSSP_ETIMEDOUT (-6)  /* a wait expired */
+#define SSSP_EUNSUPPORTED (-7)  /* size or shape not handled by the requested kernel */
+
+/* asynchronous status bits (sssp_last_status) */
+#define SSSP_STATUS_TIMEOUT 1         /* a grid barrier gave up waiting: results invalid */
+#define SSSP_STATUS_NEG_WEIGHT 2      /* a negative weight was seen: precondition violated */
+#define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps (informational) */
+
+/* flags for sssp_dense_solve_ex / batched calls */
+#define SSSP_FLAG_LITERAL 1u  /* settle one vertex per round: Algorithm 1 exactly as printed */
+#define SSSP_FLAG_SINGLE 2u   /* force the one-workgroup kernel */
+#define SSSP_FLAG_GRID 4u     /* force the persistent whole-GPU kernel */
+
+/* statistics of a finished launch (sssp_last_status `stats`, 4 entries) */
+#define SSSP_STAT_ROUNDS 0     /* rounds (one bucket of equal-dist vertices, or one vertex, each) */
+#define SSSP_STAT_SETTLED 1    /* vertices settled with finite dist = matrix rows relaxed */
+#define SSSP_STAT_FALLBACKS 2  /* rounds redone as one literal step because of zero weights */
+#define SSSP_STAT_BARRIERS 3   /* grid barriers passed (whole-GPU kernel) */
+
+/* Tuning knobs; pass NULL for the library's choice.  A zero field means "choose". */
+typedef struct sssp_tuning {
+    int32_t threads;     /* workgroup size: 256 or 1024 */
+    int32_t workgroups;  /* workgroups of the whole-GPU kernel, or of a batched launch */
+    int32_t reserved[6];
+} sssp_tuning;
+
+/* One solve of a batch: same meaning as the arguments of sssp_dense_solve_ex. */
+typedef struct sssp_instance {
+    const int32_t* W;
+    int64_t ld;
+    int32_t n;
+    int32_t src;
+    int32_t* dist;
+    int32_t* pred;
+} sssp_instance;
+
+int sssp_version(void);
+const char* sssp_last_error(void);
+const char* sssp_strerror(int code);
+
+/*
+ * Single-source solve, Algorithm 1 (Section III-A) on an n x n matrix with
+ * ld = n.  Picks the one-workgroup kernel for small n and the persistent
+ * whole-GPU kernel (one column slice per workgroup, the one-GPU form of the
+ * column division of Section III-B) otherwise.  Returns after enqueueing.
+ */
+int sssp_dense_solve(const int32_t* W, int32_t n, int32_t src, int32_t* dist, int32_t* pred,
+                     void* stream);
+
+/* As sssp_dense_solve with a row stride, SSSP_FLAG_* flags and tuning (NULL = default). */
+int sssp_dense_solve_ex(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
+                        int32_t* pred, uint32_t flags, const sssp_tuning* tuning, void* stream);
+
+/*
+ * Synchronises `stream` and reports the last solve or batch launched on it by
+ * this library: *status gets SSSP_STATUS_* bits, stats (may be NULL) gets the
+ * 4 SSSP_STAT_* counters.  Returns SSSP_EINVAL if nothing was launched on it.
+ */
+int sssp_last_status(void* stream, int32_t* status, int64_t* stats);
+
+/*
+ * Batched solve: `count` independent instances (host array of descriptors
+ * pointing at device buffers; instances may share W) in ONE persistent launch
+ * in which each workgroup pulls instances from a ticket counter and solves
+ * each one alone, largest first.  Every instance needs n <= sssp_batch_max_n().
+ */
+int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags,
+                             const sssp_tuning* tuning, void* stream);
+int32_t sssp_batch_max_n(void);
+
+/* Largest n the one-workgroup kernel accepts. */
+int32_t sssp_single_max_n(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSSP_H */

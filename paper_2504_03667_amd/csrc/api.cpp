@@ -1,0 +1,341 @@
+// C ABI of libsssp: argument validation, kernel choice, per-(device, stream)
+// scratch, status readback.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "sssp_internal.h"
+
+namespace sssp {
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SSSP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct DeviceInfo {
+    int cus = 0;
+    long long clock_khz = 0;  // wall_clock64 rate
+};
+
+struct Scratch {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    Ctl* ctl = nullptr;
+    Pub* pubs = nullptr;
+    size_t pubs_cap = 0;
+    int32_t* lists = nullptr;
+    size_t lists_cap = 0;
+    sssp_instance* inst = nullptr;  // device copy of a batch
+    int32_t* order = nullptr;
+    size_t inst_cap = 0;
+    sssp_instance* inst_h = nullptr;  // pinned staging
+    int32_t* order_h = nullptr;
+    hipEvent_t staged = nullptr;
+    bool launched = false;
+};
+
+std::mutex g_mu;
+std::vector<std::unique_ptr<Scratch>> g_scratch;
+std::vector<DeviceInfo> g_dev;
+
+int device_info(int dev, DeviceInfo& out) {
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    DeviceInfo& di = g_dev[dev];
+    if (di.cus == 0) {
+        int cus = 0, rate = 0;
+        hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(CUs)");
+        e = hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess || rate <= 0) rate = 100000;  // 100 MHz, the gfx9 constant clock
+        di.cus = cus;
+        di.clock_khz = rate;
+    }
+    out = di;
+    return SSSP_OK;
+}
+
+// Scratch of (current device, stream); created on first use.  Caller holds g_mu.
+int get_scratch(hipStream_t stream, Scratch** out, DeviceInfo* info) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (info) {
+        int rc = device_info(dev, *info);
+        if (rc) return rc;
+    }
+    for (auto& s : g_scratch)
+        if (s->device == dev && s->stream == stream) {
+            *out = s.get();
+            return SSSP_OK;
+        }
+    auto s = std::make_unique<Scratch>();
+    s->device = dev;
+    s->stream = stream;
+    e = hipMalloc(&s->ctl, ctl_size());
+    if (e != hipSuccess) return fail(SSSP_ENOMEM, "hipMalloc(control block): %s", hipGetErrorString(e));
+    e = hipMemset(s->ctl, 0, ctl_size());
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(control block)");
+    *out = s.get();
+    g_scratch.push_back(std::move(s));
+    return SSSP_OK;
+}
+
+// Grow a device buffer; waits for earlier work on the stream before freeing.
+template <class X>
+int ensure(Scratch* sc, X*& p, size_t& cap, size_t need, const char* what) {
+    if (cap >= need && p) return SSSP_OK;
+    if (p) {
+        hipError_t e = hipStreamSynchronize(sc->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    size_t n = std::max(need, cap * 2);
+    hipError_t e = hipMalloc(&p, n * sizeof(X));
+    if (e != hipSuccess) return fail(SSSP_ENOMEM, "hipMalloc(%s, %zu bytes): %s", what, n * sizeof(X),
+                                     hipGetErrorString(e));
+    cap = n;
+    return SSSP_OK;
+}
+
+long long barrier_timeout_ticks(const DeviceInfo& di) {
+    long long ms = 10000;
+    if (const char* s = getenv("SSSP_BARRIER_TIMEOUT_MS")) {
+        long long v = atoll(s);
+        if (v > 0) ms = v;
+    }
+    return di.clock_khz * ms;
+}
+
+int single_crossover() {
+    if (const char* s = getenv("SSSP_SINGLE_MAX_N")) {
+        int v = atoi(s);
+        if (v > 0) return v;
+    }
+    return 2048;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_solve_args(const int32_t* W, int64_t ld, int32_t n, int32_t src, const int32_t* dist,
+                     const int32_t* pred) {
+    if (!W || !dist || !pred) return fail(SSSP_EINVAL, "null buffer (W=%p dist=%p pred=%p)", (const void*)W,
+                                          (const void*)dist, (const void*)pred);
+    if (n < 1) return fail(SSSP_EINVAL, "n must be >= 1 (got %d)", n);
+    if (ld < n) return fail(SSSP_EINVAL, "ld (%lld) must be >= n (%d)", (long long)ld, n);
+    if (src < 0 || src >= n) return fail(SSSP_EINVAL, "src %d outside [0, %d)", src, n);
+    return SSSP_OK;
+}
+
+int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, int32_t* pred,
+          uint32_t flags, const sssp_tuning* tuning, hipStream_t stream) {
+    int rc = check_solve_args(W, ld, n, src, dist, pred);
+    if (rc) return rc;
+    if ((flags & SSSP_FLAG_SINGLE) && (flags & SSSP_FLAG_GRID))
+        return fail(SSSP_EINVAL, "SSSP_FLAG_SINGLE and SSSP_FLAG_GRID are exclusive");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch* sc = nullptr;
+    DeviceInfo di;
+    rc = get_scratch(stream, &sc, &di);
+    if (rc) return rc;
+    SolveArgs a{W, ld, n, src, dist, pred, flags & SSSP_FLAG_LITERAL, sc->ctl};
+    if (aligned16(W) && ld % 4 == 0) a.flags |= kFlagVec;
+    const bool single = (flags & SSSP_FLAG_SINGLE) ||
+                        (!(flags & SSSP_FLAG_GRID) && n <= single_crossover());
+    hipError_t e;
+    if (single) {
+        if (n > max_single_n())
+            return fail(SSSP_EUNSUPPORTED, "n=%d exceeds the one-workgroup limit %d", n, max_single_n());
+        int threads = tuning && tuning->threads ? tuning->threads : (n <= 1024 ? 256 : 1024);
+        e = launch_single(a, threads, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch(one-workgroup solve)");
+    } else {
+        int per_cu = 0;
+        // slice width: about 256 columns (1 KiB of each row) per workgroup by default
+        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 255) / 256);
+        int S = (int)(((int64_t)n + want - 1) / want);
+        S = (S + 3) & ~3;
+        if (S > max_grid_slice()) S = max_grid_slice();
+        int nwg = (int)(((int64_t)n + S - 1) / S);
+        e = (hipError_t)grid_occupancy(S, &per_cu);
+        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        const int cap = std::min(1024, per_cu * di.cus);
+        if (nwg > cap) {
+            nwg = cap;
+            S = (int)(((int64_t)n + nwg - 1) / nwg);
+            S = (S + 3) & ~3;
+            if (S > max_grid_slice())
+                return fail(SSSP_EUNSUPPORTED, "n=%d needs more than %d co-resident workgroups", n, cap);
+            nwg = (int)(((int64_t)n + S - 1) / S);
+        }
+        rc = ensure(sc, sc->pubs, sc->pubs_cap, 2 * (size_t)nwg, "exchange records");
+        if (rc) return rc;
+        rc = ensure(sc, sc->lists, sc->lists_cap, 2 * (size_t)nwg * S, "bucket lists");
+        if (rc) return rc;
+        e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, stream);
+        if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
+    }
+    sc->launched = true;
+    return SSSP_OK;
+}
+
+// Device instance array + pinned host staging for batched launches.
+int stage_capacity(Scratch* sc, size_t count) {
+    if (sc->staged) {
+        hipError_t e = hipEventSynchronize(sc->staged);  // previous upload done with the staging area
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    } else if (hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming) != hipSuccess) {
+        return fail(SSSP_EDEVICE, "hipEventCreate");
+    }
+    if (count <= sc->inst_cap) return SSSP_OK;
+    hipError_t e = hipStreamSynchronize(sc->stream);  // an earlier launch may still read the arrays
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    (void)hipFree(sc->inst);
+    (void)hipFree(sc->order);
+    (void)hipHostFree(sc->inst_h);
+    (void)hipHostFree(sc->order_h);
+    sc->inst = nullptr;
+    sc->order = nullptr;
+    sc->inst_h = nullptr;
+    sc->order_h = nullptr;
+    sc->inst_cap = 0;
+    const size_t cap = std::max<size_t>(count, 64);
+    if (hipMalloc(&sc->inst, sizeof(sssp_instance) * cap) != hipSuccess ||
+        hipMalloc(&sc->order, sizeof(int32_t) * cap) != hipSuccess ||
+        hipHostMalloc(&sc->inst_h, sizeof(sssp_instance) * cap) != hipSuccess ||
+        hipHostMalloc(&sc->order_h, sizeof(int32_t) * cap) != hipSuccess)
+        return fail(SSSP_ENOMEM, "allocating the batch instance arrays (%zu entries)", cap);
+    sc->inst_cap = cap;
+    return SSSP_OK;
+}
+
+int batched(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
+            hipStream_t stream) {
+    if (count < 0 || (count > 0 && !inst)) return fail(SSSP_EINVAL, "bad instance array");
+    if (count == 0) return SSSP_OK;
+    int threads = tuning && tuning->threads ? tuning->threads : 0;
+    int32_t nmax = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const sssp_instance& I = inst[i];
+        int rc = check_solve_args(I.W, I.ld, I.n, I.src, I.dist, I.pred);
+        if (rc) return fail(rc, "instance %d: %s", i, t_err.c_str());
+        nmax = std::max(nmax, I.n);
+    }
+    if (!threads) threads = nmax <= max_batch_n(256) ? 256 : 1024;
+    if (nmax > max_batch_n(threads))
+        return fail(SSSP_EUNSUPPORTED, "instance n=%d exceeds the batched limit %d", nmax, max_batch_n(threads));
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch* sc = nullptr;
+    DeviceInfo di;
+    int rc = get_scratch(stream, &sc, &di);
+    if (rc) return rc;
+    rc = stage_capacity(sc, (size_t)count);
+    if (rc) return rc;
+    memcpy(sc->inst_h, inst, sizeof(sssp_instance) * count);
+    for (int32_t i = 0; i < count; ++i) sc->order_h[i] = i;
+    std::stable_sort(sc->order_h, sc->order_h + count,
+                     [&](int32_t x, int32_t y) { return inst[x].n > inst[y].n; });  // largest first
+    hipError_t e = hipMemcpyAsync(sc->inst, sc->inst_h, sizeof(sssp_instance) * count, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sc->order, sc->order_h, sizeof(int32_t) * count, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(sc->staged, stream);
+    if (e != hipSuccess) return hip_fail(e, "staging the instance array");
+    int per_cu = 0;
+    e = (hipError_t)batch_occupancy(threads, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    int nwg = tuning && tuning->workgroups ? tuning->workgroups : per_cu * di.cus;
+    nwg = std::max(1, std::min(nwg, count));
+    e = launch_batch(sc->inst, count, sc->order, flags & SSSP_FLAG_LITERAL, sc->ctl, threads, nwg, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch(batched solve)");
+    sc->launched = true;
+    return SSSP_OK;
+}
+
+}  // namespace
+}  // namespace sssp
+
+using namespace sssp;
+
+extern "C" {
+
+int sssp_version(void) { return 1; }
+
+const char* sssp_last_error(void) { return t_err.c_str(); }
+
+const char* sssp_strerror(int code) {
+    switch (code) {
+        case SSSP_OK: return "ok";
+        case SSSP_EINVAL: return "invalid argument";
+        case SSSP_EDEVICE: return "HIP runtime error";
+        case SSSP_ENOMEM: return "out of device memory";
+        case SSSP_EAGAIN: return "try again";
+        case SSSP_ENOGRAPH: return "unknown graph";
+        case SSSP_ETIMEDOUT: return "timed out";
+        case SSSP_EUNSUPPORTED: return "unsupported size or shape";
+        default: return "unknown error";
+    }
+}
+
+int sssp_dense_solve(const int32_t* W, int32_t n, int32_t src, int32_t* dist, int32_t* pred, void* stream) {
+    return solve(W, n, n, src, dist, pred, 0u, nullptr, (hipStream_t)stream);
+}
+
+int sssp_dense_solve_ex(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, int32_t* pred,
+                        uint32_t flags, const sssp_tuning* tuning, void* stream) {
+    return solve(W, ld, n, src, dist, pred, flags, tuning, (hipStream_t)stream);
+}
+
+int sssp_last_status(void* stream, int32_t* status, int64_t* stats) {
+    if (!status) return fail(SSSP_EINVAL, "status is NULL");
+    Ctl c;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Scratch* sc = nullptr;
+        int rc = get_scratch((hipStream_t)stream, &sc, nullptr);
+        if (rc) return rc;
+        if (!sc->launched) return fail(SSSP_EINVAL, "nothing was launched on this stream");
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipMemcpy(&c, sc->ctl, sizeof c, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(control block)");
+    }
+    *status = (int32_t)c.status;
+    if (stats)
+        for (int i = 0; i < kStatCount; ++i) stats[i] = (int64_t)c.last[i];
+    return SSSP_OK;
+}
+
+int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags,
+                             const sssp_tuning* tuning, void* stream) {
+    return batched(inst, count, flags, tuning, (hipStream_t)stream);
+}
+
+int32_t sssp_batch_max_n(void) { return max_batch_n(1024); }
+
+int32_t sssp_single_max_n(void) { return max_single_n(); }
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// Device engine shared by the dense-matrix Dijkstra kernels (gfx950, wave64).
+//
+// Vocabulary follows Algorithm 1 of the paper (Section III-A): dist[], pred[],
+// visited[], the argmin vertex u, its distance d, and row u of the weight
+// matrix W relaxed into dist/pred.
+//
+// A workgroup owns a contiguous slice of S columns (vertices) of the matrix —
+// the single-GPU form of the paper's 1-D column division (Section III-B): it
+// keeps dist[] and visited[] of those vertices in registers and writes pred[]
+// of those vertices, so every column has exactly one writer and no atomics are
+// needed on dist or pred.
+//
+// Thread layout inside a workgroup of T threads.  The slice is cut into
+// NG = ceil(S/4) column groups of 4 (one 128-bit load each).  L lanes cover the
+// groups of one row (lane c owns groups c, c+L, ..., G of them), and the
+// T/L = P row partitions stream different rows of the current bucket at the
+// same time; partition 0 holds the slice state ("owner" threads).  After a
+// round the P partial minima are merged through LDS into the owners.
+//
+// Per-column candidate of a round: the lexicographic minimum, over the rows u
+// streamed, of the packed key (W[u][v] << 32 | u) compared as uint64.  Every
+// row of one round has the same dist d, so this equals the minimum of
+// (d + W[u][v], u): the lowest-index u wins a tie, which is what the strict
+// '<' of Algorithm 1 yields when equal-distance rows are relaxed in index
+// order.  Weights are read as uint32; INT32_MAX (no edge) then never improves
+// anything, because d + INT32_MAX >= INT32_MAX >= dist[v].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sssp {
+
+constexpr uint32_t kInf = 0x7fffffffu;
+constexpr uint64_t kNoKey = ~0ull;
+constexpr int kWave = 64;
+
+// status bits (Ctl::status)
+constexpr uint32_t kStatusTimeout = 1u;       // a grid barrier wait gave up
+constexpr uint32_t kStatusNegWeight = 2u;     // a negative weight was the best candidate of a column
+constexpr uint32_t kStatusZeroFallback = 4u;  // a zero-weight edge forced single-vertex steps
+
+// statistics slots (Ctl::acc / Ctl::last)
+enum { kStatRounds = 0, kStatSettled = 1, kStatFallbacks = 2, kStatBarriers = 3, kStatCount = 4 };
+
+// Per-launch control block in device memory.  Zeroed once when allocated;
+// every launch leaves it ready for the next (the last workgroup to finish
+// resets the barrier words and moves the accumulators into `last`).
+struct Ctl {
+    uint32_t bar;         // grid-barrier arrivals in the current launch
+    uint32_t exit;        // workgroups that finished the current launch
+    uint32_t status_acc;  // status bits OR-ed during the current launch
+    uint32_t status;      // status of the last finished launch
+    unsigned long long acc[kStatCount];
+    unsigned long long last[kStatCount];
+    unsigned long long next_item;  // work-queue ticket counter (batched kernels)
+    unsigned long long pad;
+};
+
+// One workgroup's contribution to a round, published before a grid barrier.
+struct Pub {
+    uint64_t key;    // (would-be local min dist << 32) | lowest vertex at that dist; kNoKey if none
+    uint32_t count;  // vertices of the slice at that dist, listed in the slot's list region
+    uint32_t flags;  // bit 0: a zero-weight edge from the bucket to an unvisited vertex was seen
+};
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return b < a ? b : a; }
+__device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
+    return ((uint64_t)d << 32) | v;
+}
+
+__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = umin64(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, kWave);
+    return x;
+}
+// inclusive prefix sum over the wave
+__device__ __forceinline__ uint32_t wave_scan32(uint32_t x) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(x, (unsigned)o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// LDS scratch for block-wide reductions (one slot per wave).
+template <int T>
+struct Red {
+    uint64_t k[T / kWave];
+    uint32_t a[T / kWave];
+    uint32_t b[T / kWave];
+};
+
+// Block-wide min of a 64-bit key and OR of 32-bit flags; every thread gets both.
+template <int T>
+__device__ __forceinline__ void block_min_or(uint64_t& key, uint32_t& flags, Red<T>& red) {
+    key = wave_min64(key);
+    flags = wave_or32(flags);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red.k[w] = key;
+        red.a[w] = flags;
+    }
+    __syncthreads();
+    key = red.k[0];
+    flags = red.a[0];
+#pragma unroll
+    for (int i = 1; i < T / kWave; ++i) {
+        key = umin64(key, red.k[i]);
+        flags |= red.a[i];
+    }
+    __syncthreads();
+}
+
+// Block-wide exclusive prefix sum; returns this thread's offset and the total.
+template <int T>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, Red<T>& red) {
+    const uint32_t inc = wave_scan32(x);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) red.b[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < T / kWave; ++i) {
+        const uint32_t s = red.b[i];
+        if (i < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + inc - x;
+}
+
+// Thread -> (row partition, lane) layout for a slice of S columns.
+struct Layout {
+    int L;   // lanes per row (power of two, <= T)
+    int P;   // row partitions (T / L)
+    int r;   // this thread's partition
+    int c;   // this thread's lane
+    int NG;  // column groups of 4 in the slice
+};
+
+template <int T>
+__device__ __forceinline__ Layout make_layout(int S) {
+    Layout lo;
+    lo.NG = (S + 3) >> 2;
+    int L = 1;
+    while (L < lo.NG && L < T) L <<= 1;
+    lo.L = L;
+    lo.P = T / L;
+    lo.r = threadIdx.x / L;
+    lo.c = threadIdx.x % L;
+    return lo;
+}
+
+// Columns of the slice held by one thread: G groups of 4.
+template <int G>
+struct Cols {
+    uint32_t dist[G][4];
+    uint64_t best[G][4];
+    uint32_t vis;  // bit 4k+j: visited, or not a column of the slice/matrix
+};
+
+// Stream rows list[r], list[r + P], ... (m entries in `list`, partition r) of
+// the matrix restricted to the slice into the running per-column minima, U rows
+// in flight per thread.  `width` = columns of the slice that exist in the
+// matrix (<= S).  `vec`: the row segments are 16-byte aligned (W aligned, ld and
+// the slice start multiples of 4), so whole groups are read with one 128-bit
+// load; otherwise, and for a partial last group, entries are read one by one.
+// Rows list[r], list[r + P], ... of one column group (4 columns starting at p0
+// within each row) into `best`.  FULL: the 4 entries exist and are 16-byte
+// aligned, read with one 128-bit load; otherwise only the first `valid` are read.
+template <int U, bool FULL>
+__device__ __forceinline__ void stream_group(uint64_t (&best)[4], const int32_t* __restrict__ p0, int64_t ld,
+                                             int valid, const int32_t* list, int m, int first, int step) {
+    for (int i = first; i < m; i += step * U) {
+        // past the end of the list, repeat its last row: a duplicate cannot change a minimum
+        uint32_t uu[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int idx = i + q * step;
+            uu[q] = (uint32_t)list[idx < m ? idx : m - 1];
+        }
+        uint32_t w[U][4];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int32_t* p = p0 + (int64_t)uu[q] * ld;
+            if (FULL) {
+                const int4 x = *reinterpret_cast<const int4*>(p);
+                w[q][0] = (uint32_t)x.x;
+                w[q][1] = (uint32_t)x.y;
+                w[q][2] = (uint32_t)x.z;
+                w[q][3] = (uint32_t)x.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[q][j] = j < valid ? (uint32_t)p[j] : kInf;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) best[j] = umin64(best[j], make_key(w[q][j], uu[q]));
+    }
+}
+
+template <int G, int U>
+__device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const int32_t* __restrict__ W,
+                                            int64_t ld, int64_t col0, int width, bool vec,
+                                            const int32_t* list, int m) {
+    // One column group at a time keeps only U x 4 weights live per thread.
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const int v0 = 4 * (lo.c + k * lo.L);
+        if (v0 >= width) continue;
+        const int32_t* p0 = W + col0 + v0;
+        if (vec && v0 + 3 < width)
+            stream_group<U, true>(cs.best[k], p0, ld, 4, list, m, lo.r, lo.P);
+        else
+            stream_group<U, false>(cs.best[k], p0, ld, min(4, width - v0), list, m, lo.r, lo.P);
+    }
+}
+
+// Merge the P partitions' minima into the owner threads (partition 0).
+// Only used when P > 1, which implies G == 1.  `mrg` holds T * 4 keys.
+template <int T, int G>
+__device__ __forceinline__ void merge_partitions(Cols<G>& cs, const Layout& lo, uint64_t* mrg) {
+    if (lo.P == 1) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mrg[(size_t)j * T + threadIdx.x] = cs.best[0][j];
+    __syncthreads();
+    if (lo.r == 0) {
+        for (int p = 1; p < lo.P; ++p)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                cs.best[0][j] = umin64(cs.best[0][j], mrg[(size_t)j * T + p * lo.L + lo.c]);
+    }
+    __syncthreads();
+}
+
+template <int G>
+__device__ __forceinline__ void reset_best(Cols<G>& cs) {
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cs.best[k][j] = kNoKey;
+}
+
+// Local vertex index of (k, j) for this thread.
+__device__ __forceinline__ int local_col(const Layout& lo, int k, int j) {
+    return 4 * (lo.c + k * lo.L) + j;
+}
+
+// Initialise the owned columns: dist = inf (0 at the source), not visited;
+// columns past the slice/matrix are flagged visited so they never take part.
+template <int G>
+__device__ __forceinline__ void init_cols(Cols<G>& cs, const Layout& lo, int64_t col0, int width,
+                                          int32_t src, int32_t* __restrict__ pred) {
+    cs.vis = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = local_col(lo, k, j);
+            const bool mine = lo.r == 0 && k * lo.L + lo.c < lo.NG && v < width;
+            cs.dist[k][j] = (mine && col0 + v == src) ? 0u : kInf;
+            if (!mine) cs.vis |= 1u << (4 * k + j);
+            else pred[col0 + v] = -1;
+        }
+    reset_best(cs);
+}
+
+// Lowest (dist, vertex) key among unvisited owned columns.
+template <int G>
+__device__ __forceinline__ uint64_t local_argmin(const Cols<G>& cs, const Layout& lo, int64_t col0) {
+    uint64_t key = kNoKey;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!(cs.vis >> (4 * k + j) & 1u))
+                key = umin64(key, make_key(cs.dist[k][j], (uint32_t)(col0 + local_col(lo, k, j))));
+    return key;
+}
+
+// Bitmask of unvisited owned columns whose dist equals d (the round's bucket).
+template <int G>
+__device__ __forceinline__ uint32_t bucket_mask(const Cols<G>& cs, uint32_t d) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!(cs.vis >> (4 * k + j) & 1u) && cs.dist[k][j] == d) m |= 1u << (4 * k + j);
+    return m;
+}
+
+// Candidate dist of a column from the round's minimum key (d + min weight);
+// returns kInf + something >= dist when there is no usable edge.  Sets *neg if
+// the minimum weight read as uint32 exceeds INT32_MAX (a negative weight).
+__device__ __forceinline__ uint32_t candidate(uint64_t best, uint32_t d, uint32_t& neg) {
+    const uint32_t w = (uint32_t)(best >> 32);
+    if (w > kInf) {
+        neg |= best != kNoKey ? kStatusNegWeight : 0u;
+        return 0xffffffffu;
+    }
+    return d + w;  // d < 2^31-1 and w <= 2^31-1: no wrap
+}
+
+// Zero-weight hazard of a fused round: an unvisited vertex outside the bucket
+// (dist > d) reachable from the bucket by a weight-0 edge would join the bucket
+// during the round and change the order Algorithm 1 settles it in.
+template <int G>
+__device__ __forceinline__ uint32_t zero_hazard(const Cols<G>& cs, uint32_t d) {
+    uint32_t z = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (!(cs.vis >> (4 * k + j) & 1u) && cs.dist[k][j] > d &&
+                (uint32_t)(cs.best[k][j] >> 32) == 0u)
+                z = 1;
+    return z;
+}
+
+// Apply a fused round: the bucket (mask) becomes visited; every other unvisited
+// column takes its candidate if strictly smaller (pred = the candidate's row).
+template <int G>
+__device__ __forceinline__ uint32_t commit_fused(Cols<G>& cs, const Layout& lo, int64_t col0,
+                                                 uint32_t d, uint32_t bucket,
+                                                 int32_t* __restrict__ pred) {
+    uint32_t neg = 0;
+    cs.vis |= bucket;
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (cs.vis >> (4 * k + j) & 1u) continue;
+            const uint32_t c = candidate(cs.best[k][j], d, neg);
+            if (c < cs.dist[k][j]) {
+                cs.dist[k][j] = c;
+                pred[col0 + local_col(lo, k, j)] = (int32_t)(uint32_t)cs.best[k][j];
+            }
+        }
+    reset_best(cs);
+    return neg;
+}
+
+// Would-be dist of a column if the pending fused round were applied (kNoKey-style
+// sentinel 0xffffffff for columns that are visited or in the bucket).
+template <int G>
+__device__ __forceinline__ uint32_t would_be(const Cols<G>& cs, int k, int j, uint32_t d,
+                                             uint32_t bucket, uint32_t& neg) {
+    const uint32_t bit = 1u << (4 * k + j);
+    if ((cs.vis | bucket) & bit) return 0xffffffffu;
+    const uint32_t c = candidate(cs.best[k][j], d, neg);
+    return c < cs.dist[k][j] ? c : cs.dist[k][j];
+}
+
+// Write the owned dist values back (a8: writeback).
+template <int G>
+__device__ __forceinline__ void write_dist(const Cols<G>& cs, const Layout& lo, int64_t col0, int width,
+                                           int32_t* __restrict__ dist) {
+    if (lo.r != 0) return;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k * lo.L + lo.c >= lo.NG) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = local_col(lo, k, j);
+            if (v < width) dist[col0 + v] = (int32_t)cs.dist[k][j];
+        }
+    }
+}
+
+}  // namespace sssp

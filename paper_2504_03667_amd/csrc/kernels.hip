@@ -1,0 +1,500 @@
+// Dense-matrix Dijkstra kernels for gfx950.
+//
+//   k_single  one workgroup solves one instance; the whole row is its slice.
+//   k_grid    persistent cooperative grid: every workgroup owns a column slice,
+//             one grid barrier per round (the single-GPU form of the paper's
+//             per-iteration MPI_Allreduce of the global minimum, Section III-B).
+//   k_batch   persistent grid of independent workgroups that pull instances
+//             from a ticket counter and solve each with the k_single engine.
+//
+// Every kernel runs the paper's Algorithm 1 (Section III-A) in rounds.  A round
+// takes the global minimum d of dist over unvisited vertices and the bucket B of
+// all unvisited vertices at d.  In the default ("fused") mode the whole bucket is
+// settled in one round: for each unvisited v outside B the round computes the
+// lowest (d + W[u][v], u) over u in B and applies it when strictly below
+// dist[v].  With every off-diagonal weight >= 1 this reproduces Algorithm 1 bit
+// for bit: relaxations from B produce distances > d, so B's members neither
+// change nor gain new members while Algorithm 1 settles them one by one in
+// index order, and the lexicographic minimum is exactly what its strict '<'
+// keeps.  A zero-weight edge from B to an unvisited vertex outside B breaks that
+// argument, so such a round is discarded and only the lowest-index vertex of B
+// is settled (one literal step of Algorithm 1).  In "literal" mode every round
+// is one such step, i.e. the paper's loop as printed.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "engine.h"
+#include "sssp_internal.h"
+
+namespace sssp {
+
+constexpr int kCap = 1024;  // bucket rows staged in LDS per chunk
+
+template <int T>
+struct SharedSolve {
+    Red<T> red;
+    int32_t list[kCap];
+    uint64_t mrg[4 * T];
+    uint32_t pre[T];
+    uint32_t cnt[T];
+    int32_t item;
+    uint32_t flag;
+};
+
+struct SolveStats {
+    unsigned long long rounds, settled, fallbacks, barriers;
+    uint32_t status;
+};
+
+// bit of local column v (0 <= v < width) if this thread owns it, else 0
+__device__ __forceinline__ uint32_t owner_bit(const Layout& lo, int64_t v, int width) {
+    if (v < 0 || v >= width || lo.r != 0) return 0;
+    const int64_t gi = v >> 2;
+    if (gi % lo.L != lo.c) return 0;
+    const int k = (int)(gi / lo.L);
+    return 1u << (4 * k + (int)(v & 3));
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup, whole row.
+// ---------------------------------------------------------------------------
+template <int T, int G, int U>
+__device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
+                             int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec,
+                             bool literal, SharedSolve<T>& sh, SolveStats& st) {
+    const Layout lo = make_layout<T>(n);
+    Cols<G> cs;
+    init_cols(cs, lo, 0, n, src, pred);
+    for (;;) {
+        // a2/a3: argmin over unvisited vertices, lowest index on ties
+        uint64_t key = local_argmin(cs, lo, 0);
+        uint32_t none = 0;
+        block_min_or<T>(key, none, sh.red);
+        const uint32_t d = (uint32_t)(key >> 32);
+        if (key == kNoKey || d >= kInf) break;  // a4: nothing reachable is left
+        const uint32_t u0 = (uint32_t)key;
+        uint32_t bucket;
+        uint32_t M;
+        if (literal) {
+            bucket = owner_bit(lo, u0, n);
+            M = 1;
+            if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
+            __syncthreads();
+            stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
+        } else {
+            bucket = bucket_mask(cs, d);
+            const uint32_t base = block_excl_scan<T>(__popc(bucket), M, sh.red);
+            for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
+                uint32_t rank = base;
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (bucket >> (4 * k + j) & 1u) {
+                            if (rank >= e0 && rank < e0 + kCap)
+                                sh.list[rank - e0] = local_col(lo, k, j);
+                            ++rank;
+                        }
+                __syncthreads();
+                stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
+                __syncthreads();
+            }
+        }
+        merge_partitions<T, G>(cs, lo, sh.mrg);
+        ++st.rounds;
+        if (!literal) {
+            uint32_t z = lo.r == 0 ? zero_hazard(cs, d) : 0u;
+            uint64_t dummy = kNoKey;
+            block_min_or<T>(dummy, z, sh.red);
+            if (z) {
+                // discard the fused round; settle only u0 (one literal step)
+                ++st.fallbacks;
+                st.status |= kStatusZeroFallback;
+                reset_best(cs);
+                if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
+                __syncthreads();
+                stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
+                merge_partitions<T, G>(cs, lo, sh.mrg);
+                bucket = owner_bit(lo, u0, n);
+                M = 1;
+            }
+        }
+        // a5/a6: settle the bucket and relax
+        if (lo.r == 0) st.status |= commit_fused(cs, lo, 0, d, bucket, pred);
+        else reset_best(cs);
+        st.settled += M;
+    }
+    write_dist(cs, lo, 0, n, dist);  // a8
+}
+
+template <int T, int G, int U>
+__global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int64_t ld, int32_t n,
+                                              int32_t src, int32_t* __restrict__ dist,
+                                              int32_t* __restrict__ pred, uint32_t flags,
+                                              Ctl* __restrict__ ctl) {
+    __shared__ SharedSolve<T> sh;
+    SolveStats st = {0, 0, 0, 0, 0};
+    const bool vec = (flags & kFlagVec) != 0;
+    solve_single<T, G, U>(W, ld, n, src, dist, pred, vec, (flags & kFlagLiteral) != 0, sh, st);
+    uint32_t s = st.status;
+    uint64_t dummy = kNoKey;
+    block_min_or<T>(dummy, s, sh.red);
+    if (threadIdx.x == 0) {
+        ctl->last[kStatRounds] = st.rounds;
+        ctl->last[kStatSettled] = st.settled;
+        ctl->last[kStatFallbacks] = st.fallbacks;
+        ctl->last[kStatBarriers] = 0;
+        ctl->status = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent grid: one column slice per workgroup, one grid barrier per round.
+// ---------------------------------------------------------------------------
+
+// Grid barrier: arrivals counted in ctl->bar; the b-th barrier of a launch
+// completes when bar reaches b * gridDim.x.  Agent-scope release before the
+// arrival and acquire after the wait make every workgroup's published records
+// visible to all others across XCDs.  Gives up after `timeout` wall-clock
+// ticks (returns false) so that a grid that is not co-resident cannot hang.
+template <int T>
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, uint32_t target, long long timeout,
+                                             SharedSolve<T>& sh) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > timeout) {
+                ok = 0;
+                break;
+            }
+        }
+        sh.flag = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return sh.flag != 0;
+}
+
+// The last workgroup to finish publishes the launch's statistics and resets
+// the barrier words, the ticket counter and the accumulators for the next launch.
+__device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bool add_stats) {
+    if (threadIdx.x != 0) return;
+    if (st.status) __hip_atomic_fetch_or(&ctl->status_acc, st.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (add_stats) {
+        __hip_atomic_fetch_add(&ctl->acc[kStatRounds], st.rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->acc[kStatSettled], st.settled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->acc[kStatFallbacks], st.fallbacks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctl->acc[kStatBarriers], st.barriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t prev = __hip_atomic_fetch_add(&ctl->exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {
+        for (int i = 0; i < kStatCount; ++i) {
+            ctl->last[i] = __hip_atomic_load(&ctl->acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ctl->status = __hip_atomic_exchange(&ctl->status_acc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->next_item, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Publish this workgroup's record for the next round: the lowest (dist, vertex)
+// key among `cand` (one would-be dist per owned column, 0xffffffff = excluded),
+// the vertices of the slice at that dist, and the zero-weight hazard flag.
+template <int T, int G>
+__device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layout& lo, int64_t col0,
+                                        uint32_t zero, Pub* __restrict__ pub, int32_t* __restrict__ list,
+                                        SharedSolve<T>& sh) {
+    uint64_t key = kNoKey;
+    if (lo.r == 0) {
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (cand[k][j] != 0xffffffffu)
+                    key = umin64(key, make_key(cand[k][j], (uint32_t)(col0 + local_col(lo, k, j))));
+    }
+    block_min_or<T>(key, zero, sh.red);
+    const uint32_t dmin = (uint32_t)(key >> 32);
+    uint32_t mask = 0;
+    if (lo.r == 0 && key != kNoKey && dmin < kInf) {
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (cand[k][j] == dmin) mask |= 1u << (4 * k + j);
+    }
+    uint32_t total;
+    uint32_t rank = block_excl_scan<T>(__popc(mask), total, sh.red);
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (mask >> (4 * k + j) & 1u) list[rank++] = (int32_t)(col0 + local_col(lo, k, j));
+    if (threadIdx.x == 0) {
+        pub->key = key;
+        pub->count = total;
+        pub->flags = zero;
+    }
+}
+
+template <int T, int G, int U>
+__global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
+                                            int32_t src, int32_t* __restrict__ dist,
+                                            int32_t* __restrict__ pred, uint32_t flags, int32_t S,
+                                            long long timeout, Ctl* __restrict__ ctl,
+                                            Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
+    __shared__ SharedSolve<T> sh;
+    SolveStats st = {0, 0, 0, 0, 0};
+    const bool vec = (flags & kFlagVec) != 0;
+    const bool literal = (flags & kFlagLiteral) != 0;
+    const int nwg = gridDim.x, g = blockIdx.x;
+    const int64_t col0 = (int64_t)g * S;
+    const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
+    const Layout lo = make_layout<T>(S);
+    Cols<G> cs;
+    init_cols(cs, lo, col0, width, src, pred);
+
+    // initial record: the committed state (dist[src] = 0)
+    uint32_t cand[G][4];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
+    uint32_t b = 0;  // barriers passed
+    publish<T, G>(cand, lo, col0, 0u, &pubs[g], &lists[(int64_t)g * S], sh);
+    bool ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+
+    bool pending = false;
+    uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
+    while (ok) {
+        const int slot = (b - 1) & 1;
+        const Pub* rp = pubs + (size_t)slot * nwg;
+        const int32_t* rl = lists + (size_t)slot * nwg * S;
+        Pub rec = {kNoKey, 0, 0};
+        if ((int)threadIdx.x < nwg) rec = rp[threadIdx.x];
+        uint64_t K = rec.key;
+        uint32_t Z = rec.flags;
+        block_min_or<T>(K, Z, sh.red);
+        if (pending) {
+            pending = false;
+            if (Z) {
+                // a fused round read a zero-weight edge out of its bucket: discard it
+                // and settle only the bucket's lowest-index vertex (one literal step)
+                ++st.fallbacks;
+                st.status |= kStatusZeroFallback;
+                reset_best(cs);
+                if (threadIdx.x == 0) sh.list[0] = (int32_t)pu0;
+                __syncthreads();
+                stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+                merge_partitions<T, G>(cs, lo, sh.mrg);
+                if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, owner_bit(lo, (int64_t)pu0 - col0, width), pred);
+                else reset_best(cs);
+                st.settled += 1;
+#pragma unroll
+                for (int k = 0; k < G; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
+                const int ns = b & 1;
+                publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
+                              &lists[((size_t)ns * nwg + g) * S], sh);
+                ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+                continue;
+            }
+            if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
+            else reset_best(cs);
+            st.settled += pM;
+        }
+        const uint32_t d = (uint32_t)(K >> 32);
+        if (K == kNoKey || d >= kInf) break;
+        const uint32_t u0 = (uint32_t)K;
+        ++st.rounds;
+
+        // the round's bucket: records whose local minimum equals d
+        uint32_t M;
+        uint32_t bucket;
+        if (literal) {
+            M = 1;
+            bucket = owner_bit(lo, (int64_t)u0 - col0, width);
+            if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
+            __syncthreads();
+            stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+        } else {
+            bucket = bucket_mask(cs, d);
+            const uint32_t c = ((int)threadIdx.x < nwg && (uint32_t)(rec.key >> 32) == d) ? rec.count : 0u;
+            const uint32_t pre = block_excl_scan<T>(c, M, sh.red);
+            if ((int)threadIdx.x < nwg) {
+                sh.pre[threadIdx.x] = pre;
+                sh.cnt[threadIdx.x] = c;
+            }
+            __syncthreads();
+            for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
+                const uint32_t e = e0 + threadIdx.x;
+                if (threadIdx.x < (unsigned)kCap && e < M) {
+                    // last record whose prefix is <= e (it has a non-zero count)
+                    int lo_i = 0, hi_i = nwg - 1;
+                    while (lo_i < hi_i) {
+                        const int mid = (lo_i + hi_i + 1) >> 1;
+                        if (sh.pre[mid] <= e) lo_i = mid;
+                        else hi_i = mid - 1;
+                    }
+                    sh.list[threadIdx.x] = rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
+                }
+                __syncthreads();
+                stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
+                __syncthreads();
+            }
+        }
+        merge_partitions<T, G>(cs, lo, sh.mrg);
+
+        // would-be state if this round is applied; publish it with the hazard flag
+        uint32_t neg = 0;
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cand[k][j] = would_be(cs, k, j, d, bucket, neg);
+        st.status |= neg;
+        const uint32_t zero = (!literal && lo.r == 0) ? zero_hazard(cs, d) : 0u;
+        const int ns = b & 1;
+        publish<T, G>(cand, lo, col0, zero, &pubs[(size_t)ns * nwg + g], &lists[((size_t)ns * nwg + g) * S], sh);
+        pending = true;
+        pd = d;
+        pu0 = u0;
+        pbucket = bucket;
+        pM = M;
+        ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+    }
+    if (!ok) st.status |= kStatusTimeout;
+    write_dist(cs, lo, col0, width, dist);
+    st.barriers = b;
+    uint32_t s = st.status;
+    uint64_t dummy = kNoKey;
+    block_min_or<T>(dummy, s, sh.red);
+    st.status = s;
+    finish_launch(ctl, st, g == 0);
+}
+
+// ---------------------------------------------------------------------------
+// Batched: independent workgroups pull instances from a ticket counter.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(T) void k_batch(const sssp_instance* __restrict__ inst, int32_t count,
+                                             const int32_t* __restrict__ order, uint32_t flags,
+                                             Ctl* __restrict__ ctl) {
+    __shared__ SharedSolve<T> sh;
+    SolveStats st = {0, 0, 0, 0, 0};
+    const bool literal = (flags & kFlagLiteral) != 0;
+    for (;;) {
+        if (threadIdx.x == 0)
+            sh.item = (int32_t)__hip_atomic_fetch_add(&ctl->next_item, 1ull, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int32_t i = sh.item;
+        __syncthreads();
+        if (i >= count) break;
+        const sssp_instance I = inst[order ? order[i] : i];
+        const bool vec = ((uintptr_t)I.W % 16 == 0) && (I.ld % 4 == 0);
+        const int groups = (I.n + 3) / 4;
+        if (groups <= T)
+            solve_single<T, 1, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+        else if (groups <= 2 * T)
+            solve_single<T, 2, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+        else
+            solve_single<T, 4, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+    }
+    uint32_t s = st.status;
+    uint64_t dummy = kNoKey;
+    block_min_or<T>(dummy, s, sh.red);
+    st.status = s;
+    finish_launch(ctl, st, true);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called by the C ABI in api.cpp).
+// ---------------------------------------------------------------------------
+template <int T, int G, int U>
+static hipError_t launch_single_t(const SolveArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_single<T, G, U>), dim3(1), dim3(T), 0, s, a.W, a.ld, a.n, a.src, a.dist,
+                       a.pred, a.flags, a.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_single(const SolveArgs& a, int threads, hipStream_t s) {
+    const int groups = (a.n + 3) / 4;
+    if (threads <= 256) {
+        if (groups <= 256) return launch_single_t<256, 1, 8>(a, s);
+        if (groups <= 512) return launch_single_t<256, 2, 8>(a, s);
+        if (groups <= 1024) return launch_single_t<256, 4, 8>(a, s);
+    }
+    if (groups <= 1024) return launch_single_t<1024, 1, 8>(a, s);
+    if (groups <= 2048) return launch_single_t<1024, 2, 8>(a, s);
+    if (groups <= 4096) return launch_single_t<1024, 4, 8>(a, s);
+    return hipErrorInvalidValue;
+}
+
+int max_single_n() { return 4 * 4 * 1024; }
+
+template <int T, int G, int U>
+static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs,
+                                int32_t* lists, hipStream_t s) {
+    const int32_t* W = a.W;
+    int64_t ld = a.ld;
+    int32_t n = a.n, src = a.src;
+    int32_t* dist = a.dist;
+    int32_t* pred = a.pred;
+    uint32_t flags = a.flags;
+    Ctl* ctl = a.ctl;
+    void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &pubs, &lists};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid<T, G, U>), dim3(nwg),
+                                      dim3(T), args, 0, s);
+}
+
+hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, int32_t* lists,
+                       hipStream_t s) {
+    const int groups = (S + 3) / 4;
+    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, pubs, lists, s);
+    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, pubs, lists, s);
+    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, pubs, lists, s);
+    return hipErrorInvalidValue;
+}
+
+int max_grid_slice() { return 4 * 4 * 1024; }
+
+int grid_occupancy(int slice, int* per_cu) {
+    const int groups = (slice + 3) / 4;
+    const void* f = groups <= 1024 ? reinterpret_cast<const void*>(&k_grid<1024, 1, 8>)
+                  : groups <= 2048 ? reinterpret_cast<const void*>(&k_grid<1024, 2, 8>)
+                                   : reinterpret_cast<const void*>(&k_grid<1024, 4, 8>);
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 1024, 0);
+}
+
+hipError_t launch_batch(const sssp_instance* d_inst, int32_t count, const int32_t* d_order,
+                        uint32_t flags, Ctl* ctl, int threads, int nwg, hipStream_t s) {
+    if (threads <= 256)
+        hipLaunchKernelGGL((k_batch<256>), dim3(nwg), dim3(256), 0, s, d_inst, count, d_order, flags, ctl);
+    else
+        hipLaunchKernelGGL((k_batch<1024>), dim3(nwg), dim3(1024), 0, s, d_inst, count, d_order, flags, ctl);
+    return hipGetLastError();
+}
+
+int batch_occupancy(int threads, int* per_cu) {
+    const void* f = threads <= 256 ? reinterpret_cast<const void*>(&k_batch<256>)
+                                   : reinterpret_cast<const void*>(&k_batch<1024>);
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, threads <= 256 ? 256 : 1024, 0);
+}
+
+int max_batch_n(int threads) { return 4 * 4 * (threads <= 256 ? 256 : 1024); }
+
+}  // namespace sssp
+
+namespace sssp {
+size_t ctl_size() { return sizeof(Ctl); }
+size_t pub_size() { return sizeof(Pub); }
+}  // namespace sssp

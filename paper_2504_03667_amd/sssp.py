@@ -1,0 +1,167 @@
+"""Python binding of libsssp (include/sssp.h): argument marshalling only.
+
+Every function here forwards torch device tensors (int32, on the current HIP
+device) and the current stream to the C ABI of the same name; all work runs in
+the HIP kernels.  There is no CPU fallback: if the library cannot be loaded the
+functions raise.
+"""
+import ctypes
+import os
+
+import torch  # loaded first so libsssp binds to the HIP runtime torch already uses
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libsssp.so")
+
+SSSP_OK = 0
+SSSP_EINVAL = -1
+SSSP_EDEVICE = -2
+SSSP_ENOMEM = -3
+SSSP_EAGAIN = -4
+SSSP_ENOGRAPH = -5
+SSSP_ETIMEDOUT = -6
+SSSP_EUNSUPPORTED = -7
+
+SSSP_STATUS_TIMEOUT = 1
+SSSP_STATUS_NEG_WEIGHT = 2
+SSSP_STATUS_ZERO_FALLBACK = 4
+
+SSSP_FLAG_LITERAL = 1
+SSSP_FLAG_SINGLE = 2
+SSSP_FLAG_GRID = 4
+
+SSSP_STAT_ROUNDS, SSSP_STAT_SETTLED, SSSP_STAT_FALLBACKS, SSSP_STAT_BARRIERS = range(4)
+
+INF = 0x7FFFFFFF
+
+
+class SsspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class sssp_tuning(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class sssp_instance(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_void_p), ("ld", ctypes.c_int64), ("n", ctypes.c_int32),
+                ("src", ctypes.c_int32), ("dist", ctypes.c_void_p), ("pred", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsssp.so; builds it in-tree if it is not there yet."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(SO)
+        P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.sssp_version.restype = ctypes.c_int
+        L.sssp_last_error.restype = ctypes.c_char_p
+        L.sssp_strerror.argtypes = [ctypes.c_int]
+        L.sssp_strerror.restype = ctypes.c_char_p
+        L.sssp_dense_solve.argtypes = [P, I32, I32, P, P, P]
+        L.sssp_dense_solve_ex.argtypes = [P, I64, I32, I32, P, P, U32, ctypes.POINTER(sssp_tuning), P]
+        L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+        L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
+                                               ctypes.POINTER(sssp_tuning), P]
+        L.sssp_batch_max_n.restype = I32
+        L.sssp_single_max_n.restype = I32
+        for name in ("sssp_dense_solve", "sssp_dense_solve_ex", "sssp_last_status",
+                     "sssp_dense_solve_batched"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SSSP_OK:
+        msg = lib().sssp_last_error().decode(errors="replace")
+        raise SsspError(rc, msg or lib().sssp_strerror(rc).decode())
+    return rc
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise TypeError("%s must be an int32 tensor on the GPU" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _tuning(threads=0, workgroups=0):
+    if not threads and not workgroups:
+        return None
+    t = sssp_tuning()
+    t.threads, t.workgroups = threads, workgroups
+    return ctypes.byref(t)
+
+
+def sssp_dense_solve(W, n, src, dist, pred, stream=None):
+    """sssp_dense_solve: W is an int32 [n, n] contiguous device tensor."""
+    if W.dim() != 2 or W.shape[0] != n or W.shape[1] != n or not W.is_contiguous():
+        raise ValueError("W must be a contiguous [n, n] tensor")
+    return _check(lib().sssp_dense_solve(_ptr(W, "W"), n, src, _ptr(dist, "dist"),
+                                         _ptr(pred, "pred"), _stream(stream)))
+
+
+def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroups=0, stream=None):
+    """sssp_dense_solve_ex: W is an int32 device tensor holding n rows of stride ld."""
+    if W.numel() < (n - 1) * ld + n:
+        raise ValueError("W is too small for n rows of stride ld")
+    return _check(lib().sssp_dense_solve_ex(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
+                                            _ptr(pred, "pred"), flags,
+                                            _tuning(threads, workgroups), _stream(stream)))
+
+
+def sssp_last_status(stream=None):
+    """Synchronises the stream; returns (status bits, [rounds, settled, fallbacks, barriers])."""
+    st = ctypes.c_int32(0)
+    stats = (ctypes.c_int64 * 4)()
+    _check(lib().sssp_last_status(_stream(stream), ctypes.byref(st), stats))
+    return st.value, list(stats)
+
+
+def make_instances(items):
+    """items: iterable of (W, src, dist, pred) with W an int32 [n, ld] device tensor."""
+    items = list(items)
+    arr = (sssp_instance * max(1, len(items)))()
+    for i, (W, src, dist, pred) in enumerate(items):
+        n = W.shape[0]
+        if dist.numel() < n or pred.numel() < n:
+            raise ValueError("dist/pred too small for instance %d" % i)
+        arr[i].W = _ptr(W, "W").value
+        arr[i].ld = W.stride(0)
+        arr[i].n = n
+        arr[i].src = src
+        arr[i].dist = _ptr(dist, "dist").value
+        arr[i].pred = _ptr(pred, "pred").value
+    return arr, len(items)
+
+
+def sssp_dense_solve_batched(items, flags=0, threads=0, workgroups=0, stream=None):
+    """sssp_dense_solve_batched over (W, src, dist, pred) tuples, one launch."""
+    arr, count = make_instances(items)
+    return _check(lib().sssp_dense_solve_batched(arr, count, flags, _tuning(threads, workgroups),
+                                                 _stream(stream)))
+
+
+# ---- convenience wrappers (allocate outputs, return tensors) ----
+
+def solve(W, src, flags=0, threads=0, workgroups=0, stream=None):
+    """Solve from `src` on the int32 [n, ld] device tensor W; returns (dist, pred) tensors."""
+    n = W.shape[0]
+    dist = torch.empty(n, dtype=torch.int32, device=W.device)
+    pred = torch.empty(n, dtype=torch.int32, device=W.device)
+    sssp_dense_solve_ex(W, W.stride(0), n, src, dist, pred, flags, threads, workgroups, stream)
+    return dist, pred

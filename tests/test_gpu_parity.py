@@ -1,0 +1,218 @@
+"""GPU parity: dist and pred of the HIP kernels, called through the C ABI, must equal
+the CPU oracle's bit for bit (integer arithmetic throughout)."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests.graphs import INF, from_edges, golden_cases, random_dense
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_03667_amd as m
+    m.lib()
+    return m
+
+
+MODES = {
+    "single": 2,           # SSSP_FLAG_SINGLE
+    "grid": 4,             # SSSP_FLAG_GRID
+    "single_literal": 3,
+    "grid_literal": 5,
+}
+
+
+def run(sp, Wt, src, flags, workgroups=0, threads=0):
+    dist, pred = sp.solve(Wt, src, flags=flags, workgroups=workgroups, threads=threads)
+    status, stats = sp.sssp_last_status()
+    return dist.cpu().numpy(), pred.cpu().numpy(), status, stats
+
+
+def check(sp, W, src, flags, tag="", workgroups=0, threads=0, Wt=None):
+    if Wt is None:
+        Wt = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    d, p, status, stats = run(sp, Wt, src, flags, workgroups, threads)
+    dr, pr, relaxed = oracle.dijkstra(W, src)
+    assert status & 3 == 0, (tag, "status", status)
+    bad = np.nonzero((d != dr) | (p != pr))[0]
+    assert bad.size == 0, (tag, "n", W.shape[0], "src", src, "first mismatches", bad[:5].tolist(),
+                           d[bad[:5]].tolist(), dr[bad[:5]].tolist(), p[bad[:5]].tolist(),
+                           pr[bad[:5]].tolist())
+    assert stats[1] == relaxed, (tag, "settled", stats[1], relaxed)
+    return stats
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_worked_examples(sp, mode):
+    for name, W, expect in golden_cases():
+        for src, e in expect.items():
+            Wt = torch.from_numpy(W).cuda()
+            d, p, status, _ = run(sp, Wt, src, MODES[mode])
+            assert d.tolist() == e["dist"] and p.tolist() == e["pred"], (name, src, mode)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_random_sizes_and_tails(sp, mode):
+    rng = np.random.default_rng(100)
+    sizes = [1, 2, 3, 4, 5, 7, 63, 64, 65, 127, 128, 129, 255, 257, 1000, 1023, 1025, 2047, 4097]
+    for i, n in enumerate(sizes):
+        if "single" in mode and n > 16384:
+            continue
+        p = float(rng.choice([0.01, 0.05, 0.3, 0.9]))
+        W = random_dense(rng, n, p, 1, int(rng.choice([1, 3, 100])), directed=bool(i % 2))
+        for src in sorted({0, n // 2, n - 1}):
+            check(sp, W, src, MODES[mode], tag=(mode, n, p))
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_zero_weights_and_ties(sp, mode):
+    rng = np.random.default_rng(101)
+    for i in range(12):
+        n = int(rng.choice([5, 40, 300, 1100]))
+        W = random_dense(rng, n, 0.2, 1, 2, directed=bool(i % 2), zero_prob=0.1)
+        check(sp, W, int(rng.integers(0, n)), MODES[mode], tag=(mode, "zero", n))
+    # builder-made regression: naive fusion would set pred[2] = 4
+    Z = from_edges(5, [(0, 3, 1), (0, 4, 1), (3, 1, 0), (1, 2, 1), (4, 2, 1)])
+    check(sp, Z, 0, MODES[mode], tag=(mode, "zero-regression"))
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_degenerate_graphs(sp, mode):
+    n = 777
+    # complete graph with equal weights (maximal ties)
+    K = np.full((n, n), 5, np.int32)
+    np.fill_diagonal(K, 0)
+    check(sp, K, 13, MODES[mode], tag="complete")
+    # no edges at all: isolated source
+    E = np.full((n, n), INF, np.int32)
+    np.fill_diagonal(E, 0)
+    check(sp, E, 400, MODES[mode], tag="empty")
+    # two components
+    rng = np.random.default_rng(102)
+    W = random_dense(rng, n, 0.05, 1, 9)
+    W[:300, 300:] = INF
+    W[300:, :300] = INF
+    check(sp, W, 10, MODES[mode], tag="components")
+    check(sp, W, 500, MODES[mode], tag="components2")
+    # path graph: n - 1 rounds
+    P = from_edges(n, [(i, i + 1, 1 + i % 3) for i in range(n - 1)])
+    check(sp, P, 0, MODES[mode], tag="path")
+
+
+@pytest.mark.parametrize("mode", ["single", "grid"])
+def test_row_stride_and_unaligned(sp, mode):
+    rng = np.random.default_rng(103)
+    for n, ld in ((301, 304), (301, 301), (513, 515), (1000, 1001)):
+        W = random_dense(rng, n, 0.05, 1, 50)
+        big = np.full((n, ld), INF, np.int32)
+        big[:, :n] = W
+        Wt = torch.from_numpy(big).cuda()
+        dist = torch.empty(n, dtype=torch.int32, device="cuda")
+        pred = torch.empty(n, dtype=torch.int32, device="cuda")
+        sp.sssp_dense_solve_ex(Wt, ld, n, 7, dist, pred, MODES[mode])
+        status, _ = sp.sssp_last_status()
+        dr, pr, _ = oracle.dijkstra(W, 7)
+        assert status & 3 == 0
+        assert np.array_equal(dist.cpu().numpy(), dr) and np.array_equal(pred.cpu().numpy(), pr)
+
+
+def test_grid_workgroup_counts(sp):
+    rng = np.random.default_rng(104)
+    W = random_dense(rng, 3000, 0.02, 1, 20)
+    Wt = torch.from_numpy(W).cuda()
+    for wg in (1, 2, 3, 7, 64, 100, 256, 750):
+        check(sp, W, 5, MODES["grid"], tag=("wg", wg), workgroups=wg, Wt=Wt)
+
+
+def test_single_thread_counts(sp):
+    rng = np.random.default_rng(105)
+    for n in (100, 1024, 3000, 4096, 8000, 16384):
+        W = random_dense(rng, n, 0.01, 1, 30)
+        Wt = torch.from_numpy(W).cuda()
+        for threads in (256, 1024):
+            if threads == 256 and n > 4096:
+                continue
+            check(sp, W, 1, MODES["single"], tag=("threads", threads, n), threads=threads, Wt=Wt)
+
+
+def test_rounds_equal_distinct_distances(sp):
+    spec = gen.GraphSpec(2000, 0.05, 1, 100, 77)
+    W = gen.dense_host(spec)
+    for mode in ("single", "grid"):
+        stats = check(sp, W, 0, MODES[mode], tag="rounds")
+        d, _, _ = oracle.dijkstra(W, 0)
+        assert stats[0] == len({int(x) for x in d if x != INF})
+        assert stats[2] == 0
+
+
+def test_small_workload_all_modes(sp):
+    """n=1024 undirected, p=0.1, weights in [1,100], source 0 (all kernels, both modes)."""
+    wl = gen.workload_single_small()
+    W = gen.dense_host(wl.graphs[0])
+    Wt = torch.from_numpy(W).cuda()
+    for mode, flags in MODES.items():
+        check(sp, W, 0, flags, tag=mode, Wt=Wt)
+    for src in (1, 511, 1023):
+        check(sp, W, src, 0, tag="default", Wt=Wt)
+
+
+def test_medium_workload_full_oracle(sp):
+    """n=16384, p=0.01, weights in [1,100]: undirected and directed, sources 0, 7, 12345."""
+    wl = gen.workload_single_medium()
+    for gi, spec in enumerate(wl.graphs):
+        W = gen.dense_host(spec)
+        Wt = gen.dense_device(spec)
+        assert gen.checksum_device(Wt) == gen.checksum_host(W)
+        for g2, src in wl.instances:
+            if g2 != gi:
+                continue
+            check(sp, W, src, 0, tag=("medium", gi, src), Wt=Wt)
+        del Wt
+        torch.cuda.empty_cache()
+
+
+def test_determinism(sp):
+    spec = gen.GraphSpec(5000, 0.02, 1, 10, 55)
+    Wt = gen.dense_device(spec)
+    ref = None
+    for rep in range(20):
+        d, p, status, _ = run(sp, Wt, 17, 0)
+        if ref is None:
+            ref = (d, p)
+        assert np.array_equal(d, ref[0]) and np.array_equal(p, ref[1])
+
+
+def test_batched_matches_alone(sp):
+    """Every instance of a batch equals its own solve alone and the oracle."""
+    rng = np.random.default_rng(106)
+    graphs = []
+    for i in range(12):
+        n = int(rng.integers(1, 5000)) if i else 4100
+        graphs.append(random_dense(rng, n, float(rng.uniform(0.005, 0.3)), 1, 100,
+                                   directed=bool(i % 3 == 0), zero_prob=0.05 if i == 5 else 0.0))
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    items, refs = [], []
+    for gi, W in enumerate(graphs):
+        for src in sorted({0, W.shape[0] - 1, W.shape[0] // 3}):
+            n = W.shape[0]
+            dist = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+            pred = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+            items.append((dev[gi], src, dist, pred))
+            refs.append((gi, src))
+    for flags in (0, 1):
+        sp.sssp_dense_solve_batched(items, flags=flags)
+        status, stats = sp.sssp_last_status()
+        assert status & 3 == 0
+        total = 0
+        for (Wt, src, dist, pred), (gi, s) in zip(items, refs):
+            dr, pr, rel = oracle.dijkstra(graphs[gi], s)
+            total += rel
+            assert np.array_equal(dist.cpu().numpy(), dr) and np.array_equal(pred.cpu().numpy(), pr)
+        assert stats[1] == total
