@@ -1,0 +1,250 @@
+"""Benchmark of the dense-matrix Dijkstra hot path on one MI355X.
+
+One step = one single-source solve (the whole n-iteration loop of Algorithm 1:
+argmin, settle, relax row u into dist/pred, writeback) of the n=65536
+undirected G(n, 0.5) graph with weights in [1, 1000] (16 GiB int32 matrix,
+resident in HBM before timing), source 0.  `value` = matrix entries scanned
+per second = n * (rows relaxed) / time per step.
+
+The same JSON line carries the other workloads: n=16384 (undirected and
+directed, sources 0/7/12345), n=1024 latency, and the batched launch of 320
+instances against one-solve-per-launch; plus the HBM roofline of the
+whole-GPU kernel and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--only-large", action="store_true", help="time only the n=65536 workload")
+    ap.add_argument("--cpu-iters", type=int, default=32768,
+                    help="iterations of the oracle timed for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 4 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def timed_solves(sp, torch, Wt, src, steps, warmup, flags=0):
+    n = Wt.shape[0]
+    dist = torch.empty(n, dtype=torch.int32, device=Wt.device)
+    pred = torch.empty(n, dtype=torch.int32, device=Wt.device)
+    for _ in range(warmup):
+        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    status, stats = sp.sssp_last_status()
+    if status & 3:
+        raise RuntimeError("kernel status %d" % status)
+    return {"ms_per_step": wall / steps * 1e3, "kernel_ms": kern, "stats": stats,
+            "dist": dist, "pred": pred}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def read_traffic(name):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if its
+    kernel-source hash matches the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t:
+        return None
+    from paper_2504_03667_amd.build import source_hash
+    if m.group(1) != source_hash():
+        return None
+    return float(t.group(1))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the dense-matrix Dijkstra path here runs on a "
+              "single MI355X (--gpus %d requested). Multi-GPU column sharding is described in "
+              "DESIGN.md and not implemented." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2504_03667_amd as sp
+
+    sp.lib()
+    if args.copy_calibration:
+        # a copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
+        a = torch.empty(1 << 30, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # ---- n = 65536, p = 0.5, 16 GiB: the headline -------------------------------
+    wl = gen.workload_single_large()
+    spec = wl.graphs[0]
+    print("[bench] generating n=%d matrix on the GPU" % spec.n, file=sys.stderr, flush=True)
+    Wt = gen.dense_device(spec)
+    torch.cuda.synchronize()
+    print("[bench] timing %d steps (+%d warmup)" % (args.steps, args.warmup), file=sys.stderr, flush=True)
+    r = timed_solves(sp, torch, Wt, 0, args.steps, args.warmup)
+    trace = sp.sssp_last_trace()
+    n = spec.n
+    R = r["stats"][1]
+    rounds = r["stats"][0]
+    entries = n * R
+    ms = r["ms_per_step"]
+    kern_ms = sum(r["kernel_ms"]) / len(r["kernel_ms"])
+    alg_bytes = 4.0 * n * R + 8.0 * n
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = read_traffic("k_grid_n65536_counters.txt")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_grid (whole-GPU persistent solve)", "kernel_ms": round(kern_ms, 4),
+                "algorithmic_bytes_per_launch": alg_bytes}
+    round_us = [round((trace[i + 1][0] - trace[i][0]) / 1e3, 1) for i in range(len(trace) - 1)]
+    large = {"n": n, "rows_relaxed": R, "rounds": rounds, "barriers": r["stats"][3],
+             "round_rows": [t[1] for t in trace[:-1]], "round_us": round_us,
+             "ms_per_solve": round(ms, 4), "entries_per_s": entries / (ms * 1e-3),
+             "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1)}
+    # literal mode once: one vertex per grid barrier (Algorithm 1 as printed)
+    if not args.only_large:
+        lit = timed_solves(sp, torch, Wt, 0, 1, 0, flags=sp.SSSP_FLAG_LITERAL)
+        large["literal_ms_per_solve"] = round(lit["ms_per_step"], 2)
+        large["literal_us_per_barrier"] = round(lit["ms_per_step"] * 1e3 / max(1, lit["stats"][3]), 3)
+        del lit
+    dist_large = r["dist"].cpu().numpy()
+    del Wt, r
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.only_large:
+        # ---- n = 16384, p = 0.01: undirected and directed, three sources ----------
+        wl2 = gen.workload_single_medium()
+        med = []
+        for gi, g in enumerate(wl2.graphs):
+            Wm = gen.dense_device(g)
+            for g2, src in wl2.instances:
+                if g2 != gi:
+                    continue
+                rr = timed_solves(sp, torch, Wm, src, 10, 2)
+                med.append({"directed": g.directed, "src": src, "ms_per_solve": round(rr["ms_per_step"], 4),
+                            "rows_relaxed": rr["stats"][1], "rounds": rr["stats"][0],
+                            "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3)})
+            del Wm
+        extra["n16384"] = med
+        torch.cuda.empty_cache()
+
+        # ---- n = 1024, p = 0.1: latency of one solve ------------------------------
+        g1 = gen.workload_single_small().graphs[0]
+        W1 = gen.dense_device(g1)
+        rr = timed_solves(sp, torch, W1, 0, 200, 10)
+        extra["n1024"] = {"median_us": round(1e3 * percentile(rr["kernel_ms"], 50), 2),
+                          "p99_us": round(1e3 * percentile(rr["kernel_ms"], 99), 2),
+                          "rounds": rr["stats"][0]}
+        del W1
+
+        # ---- batched: 320 instances in one launch vs one solve per launch ---------
+        wl4 = gen.workload_batched()
+        mats = [gen.dense_device(g) for g in wl4.graphs]
+        items = []
+        for gi, src in wl4.instances:
+            nn = wl4.graphs[gi].n
+            items.append((mats[gi], src, torch.empty(nn, dtype=torch.int32, device="cuda"),
+                          torch.empty(nn, dtype=torch.int32, device="cuda")))
+        for _ in range(2):
+            sp.sssp_dense_solve_batched(items)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            sp.sssp_dense_solve_batched(items)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        status, bstats = sp.sssp_last_status()
+        tb = sorted(times)[len(times) // 2]
+        # plain path: one sssp_dense_solve per instance, synchronised each time
+        t0 = time.perf_counter()
+        for W_, src, dist_, pred_ in items:
+            sp.sssp_dense_solve_ex(W_, W_.stride(0), W_.shape[0], src, dist_, pred_, 0)
+            torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        extra["batched"] = {"instances": len(items), "launch_ms": round(tb * 1e3, 3),
+                            "solves_per_s": round(len(items) / tb, 1),
+                            "plain_solves_per_s": round(len(items) / tp, 1),
+                            "speedup_vs_plain": round(tp / tb, 3), "status": status,
+                            "rows_relaxed": bstats[1]}
+        del mats, items
+        torch.cuda.empty_cache()
+
+    # ---- CPU oracle on a bounded sample of the headline workload -----------------
+    cpu = None
+    if not args.skip_cpu:
+        import oracle
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        Wh = gen.dense_host(spec)
+        t0 = time.perf_counter()
+        rel = oracle.dijkstra_prefix(Wh, 0, args.cpu_iters)
+        dt = time.perf_counter() - t0
+        cpu = {"value": n * rel / dt, "unit": "matrix entries scanned/s", "cores": 1, "kind": "oracle",
+               "sample": "first %d of %d iterations of Algorithm 1 (serial C, one thread) on the "
+                         "n=65536 p=0.5 source-0 solve, %.1f s" % (args.cpu_iters, n, dt)}
+        del Wh
+
+    line = {
+        "metric": "matrix entries scanned/s (single-source dense Dijkstra, n=65536)",
+        "value": entries / (ms * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic: seeded counter-based G(n,p) matrices generated in HBM",
+        "config": {"workload": wl.name, "n": n, "p": spec.p, "weights": [spec.lo, spec.hi],
+                   "directed": spec.directed, "src": 0, "matrix_bytes": 4 * n * n,
+                   "parallelism": "single GPU, persistent cooperative grid"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "large": large,
+    }
+    line.update(extra)
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -108,6 +108,15 @@ int sssp_dense_solve_ex(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
 int sssp_last_status(void* stream, int32_t* status, int64_t* stats);
 
 /*
+ * Per-round trace of the last one-workgroup or whole-GPU solve on `stream`
+ * (synchronises it): t_ns[i] = start of round i in ns after the start of
+ * round 0, t_ns[count] = end of the solve, rows[i] = matrix rows streamed in
+ * round i (rows[count] = -1).  Writes min(count + 1, cap) entries; *count gets
+ * the number of rounds recorded (at most 256).  A debugging and tuning aid.
+ */
+int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int32_t* count);
+
+/*
  * Batched solve: `count` independent instances (host array of descriptors
  * pointing at device buffers; instances may share W) in ONE persistent launch
  * in which each workgroup pulls instances from a ticket counter and solves

@@ -38,6 +38,9 @@ def lib():
         L.oracle_dijkstra.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P, P,
                                       ctypes.c_int32]
         L.oracle_dijkstra.restype = ctypes.c_int64
+        L.oracle_dijkstra_iters.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P,
+                                            P, ctypes.c_int32, ctypes.c_int32]
+        L.oracle_dijkstra_iters.restype = ctypes.c_int64
         L.oracle_floyd_warshall.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P]
         L.oracle_floyd_warshall.restype = ctypes.c_int
         L.oracle_bellman_ford.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
@@ -77,6 +80,19 @@ def dijkstra(W, src, early_exit=True, with_order=False):
     if with_order:
         return dist, pred, order, int(r)
     return dist, pred, int(r)
+
+
+def dijkstra_prefix(W, src, iters):
+    """The first `iters` iterations of Algorithm 1 (a timing sample); returns rows relaxed."""
+    W, ld = _mat(W)
+    n = W.shape[0]
+    dist = np.empty(n, np.int32)
+    pred = np.empty(n, np.int32)
+    r = lib().oracle_dijkstra_iters(W.ctypes.data, ld, n, src, dist.ctypes.data, pred.ctypes.data,
+                                    None, 1, int(iters))
+    if r < 0:
+        raise ValueError("oracle_dijkstra_iters rejected the arguments")
+    return int(r)
 
 
 def floyd_warshall(W):

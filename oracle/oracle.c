@@ -42,11 +42,13 @@
  * outputs are identical either way.
  *
  * order (optional, n entries): settle order, -1 past the last settled vertex.
+ * max_iters > 0 stops after that many iterations (a timing sample of the same
+ * loop; the outputs are then partial).
  * Returns the number of settled vertices whose dist was finite (rows relaxed),
  * or -1 on bad arguments.
  */
-int64_t oracle_dijkstra(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
-                        int32_t* pred, int32_t* order, int32_t early_exit)
+int64_t oracle_dijkstra_iters(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
+                              int32_t* pred, int32_t* order, int32_t early_exit, int32_t max_iters)
 {
     if (!W || !dist || !pred || n < 1 || ld < n || src < 0 || src >= n) return -1;
     unsigned char* visited = (unsigned char*)calloc((size_t)n, 1);
@@ -58,7 +60,8 @@ int64_t oracle_dijkstra(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
     }
     dist[src] = 0;
     int64_t relaxed = 0;
-    for (int32_t i = 0; i < n; ++i) {
+    const int32_t iters = (max_iters > 0 && max_iters < n) ? max_iters : n;
+    for (int32_t i = 0; i < iters; ++i) {
         int32_t u = -1;
         for (int32_t v = 0; v < n; ++v)
             if (!visited[v] && (u < 0 || dist[v] < dist[u])) u = v;
@@ -78,6 +81,12 @@ int64_t oracle_dijkstra(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
     }
     free(visited);
     return relaxed;
+}
+
+int64_t oracle_dijkstra(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
+                        int32_t* pred, int32_t* order, int32_t early_exit)
+{
+    return oracle_dijkstra_iters(W, ld, n, src, dist, pred, order, early_exit, 0);
 }
 
 /* Textbook Floyd-Warshall over the matrix; D is n x n int64, OR_INF64 = no path.

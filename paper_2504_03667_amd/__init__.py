@@ -7,10 +7,10 @@ from .sssp import (INF, SSSP_FLAG_GRID, SSSP_FLAG_LITERAL, SSSP_FLAG_SINGLE, SSS
                    SSSP_STAT_FALLBACKS, SSSP_STAT_ROUNDS, SSSP_STAT_SETTLED,
                    SSSP_STATUS_NEG_WEIGHT, SSSP_STATUS_TIMEOUT, SSSP_STATUS_ZERO_FALLBACK,
                    SsspError, lib, solve, sssp_dense_solve, sssp_dense_solve_batched,
-                   sssp_dense_solve_ex, sssp_last_status)
+                   sssp_dense_solve_ex, sssp_last_status, sssp_last_trace)
 
 __all__ = ["INF", "SSSP_FLAG_GRID", "SSSP_FLAG_LITERAL", "SSSP_FLAG_SINGLE", "SSSP_STAT_BARRIERS",
            "SSSP_STAT_FALLBACKS", "SSSP_STAT_ROUNDS", "SSSP_STAT_SETTLED",
            "SSSP_STATUS_NEG_WEIGHT", "SSSP_STATUS_TIMEOUT", "SSSP_STATUS_ZERO_FALLBACK",
            "SsspError", "lib", "solve", "sssp_dense_solve", "sssp_dense_solve_batched",
-           "sssp_dense_solve_ex", "sssp_last_status"]
+           "sssp_dense_solve_ex", "sssp_last_status", "sssp_last_trace"]

@@ -45,3 +45,16 @@ def build(verbose=False):
 
 if __name__ == "__main__":
     build(verbose=True)
+
+
+def source_hash():
+    """Short hash of the kernel and ABI sources (ties profiles to the code they measured)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "sssp.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]

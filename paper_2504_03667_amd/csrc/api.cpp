@@ -122,13 +122,25 @@ int ensure(Scratch* sc, X*& p, size_t& cap, size_t need, const char* what) {
     return SSSP_OK;
 }
 
+// Grid-barrier wait limit, SSSP_BARRIER_TIMEOUT_US microseconds (default 10 s).
+// A wait that exceeds it ends the solve with SSSP_STATUS_TIMEOUT instead of
+// hanging; 0 makes every wait give up at once (used to test that path).
 long long barrier_timeout_ticks(const DeviceInfo& di) {
-    long long ms = 10000;
-    if (const char* s = getenv("SSSP_BARRIER_TIMEOUT_MS")) {
-        long long v = atoll(s);
-        if (v > 0) ms = v;
+    long long us = 10000000;
+    if (const char* s = getenv("SSSP_BARRIER_TIMEOUT_US")) {
+        char* end = nullptr;
+        long long v = strtoll(s, &end, 10);
+        if (end != s && v >= 0) us = v;
     }
-    return di.clock_khz * ms;
+    return di.clock_khz * us / 1000;
+}
+
+// SSSP_GRID_LAUNCH=plain: launch the whole-GPU kernel with an ordinary launch
+// (grid bounded by the occupancy query) instead of a cooperative one; profilers
+// that cannot finish after cooperative launches need it.
+bool plain_grid_launch() {
+    const char* s = getenv("SSSP_GRID_LAUNCH");
+    return s && strcmp(s, "plain") == 0;
 }
 
 int single_crossover() {
@@ -196,7 +208,7 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         if (rc) return rc;
         rc = ensure(sc, sc->lists, sc->lists_cap, 2 * (size_t)nwg * S, "bucket lists");
         if (rc) return rc;
-        e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, stream);
+        e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, plain_grid_launch(), stream);
         if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
     }
     sc->launched = true;
@@ -326,6 +338,31 @@ int sssp_last_status(void* stream, int32_t* status, int64_t* stats) {
     *status = (int32_t)c.status;
     if (stats)
         for (int i = 0; i < kStatCount; ++i) stats[i] = (int64_t)c.last[i];
+    return SSSP_OK;
+}
+
+int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int32_t* count) {
+    if (!count || cap < 0 || (cap > 0 && (!t_ns || !rows))) return fail(SSSP_EINVAL, "bad trace buffers");
+    Ctl c;
+    DeviceInfo di;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Scratch* sc = nullptr;
+        int rc = get_scratch((hipStream_t)stream, &sc, &di);
+        if (rc) return rc;
+        if (!sc->launched) return fail(SSSP_EINVAL, "nothing was launched on this stream");
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipMemcpy(&c, sc->ctl, sizeof c, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(control block)");
+    }
+    const int32_t nr = (int32_t)std::min<uint32_t>(c.trace_n, kTraceCap);
+    const int32_t k = std::min(nr + 1, cap);
+    for (int32_t i = 0; i < k; ++i) {
+        t_ns[i] = (int64_t)((c.trace_t[i] - c.trace_t[0]) * 1000000.0 / (double)di.clock_khz);
+        rows[i] = i < nr ? (int32_t)c.trace_m[i] : -1;
+    }
+    *count = nr;
     return SSSP_OK;
 }
 

@@ -42,18 +42,27 @@ constexpr uint32_t kStatusZeroFallback = 4u;  // a zero-weight edge forced singl
 // statistics slots (Ctl::acc / Ctl::last)
 enum { kStatRounds = 0, kStatSettled = 1, kStatFallbacks = 2, kStatBarriers = 3, kStatCount = 4 };
 
+constexpr int kTraceCap = 256;  // rounds recorded per launch (round start time, bucket size)
+
 // Per-launch control block in device memory.  Zeroed once when allocated;
 // every launch leaves it ready for the next (the last workgroup to finish
-// resets the barrier words and moves the accumulators into `last`).
+// resets the barrier words and moves the accumulators into `last`).  The
+// arrival counter and the release word the waiters poll sit on separate
+// 128-byte lines so that polling does not contend with the arrivals.
 struct Ctl {
-    uint32_t bar;         // grid-barrier arrivals in the current launch
+    uint32_t bar;  // grid-barrier arrivals in the current launch
+    uint32_t pad0[31];
+    uint32_t gen;  // number of the last completed grid barrier of the current launch
+    uint32_t pad1[31];
     uint32_t exit;        // workgroups that finished the current launch
     uint32_t status_acc;  // status bits OR-ed during the current launch
     uint32_t status;      // status of the last finished launch
+    uint32_t trace_n;     // rounds recorded in trace_t / trace_m by the last launch
     unsigned long long acc[kStatCount];
     unsigned long long last[kStatCount];
     unsigned long long next_item;  // work-queue ticket counter (batched kernels)
-    unsigned long long pad;
+    long long trace_t[kTraceCap + 1];  // wall-clock ticks at the start of each round, then the end
+    uint32_t trace_m[kTraceCap];       // rows streamed in each round
 };
 
 // One workgroup's contribution to a round, published before a grid barrier.

@@ -61,7 +61,7 @@ __device__ __forceinline__ uint32_t owner_bit(const Layout& lo, int64_t v, int w
 template <int T, int G, int U>
 __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                              int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec,
-                             bool literal, SharedSolve<T>& sh, SolveStats& st) {
+                             bool literal, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
     const Layout lo = make_layout<T>(n);
     Cols<G> cs;
     init_cols(cs, lo, 0, n, src, pred);
@@ -73,6 +73,7 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
         const uint32_t d = (uint32_t)(key >> 32);
         if (key == kNoKey || d >= kInf) break;  // a4: nothing reachable is left
         const uint32_t u0 = (uint32_t)key;
+        const long long t_round = wall_clock64();
         uint32_t bucket;
         uint32_t M;
         if (literal) {
@@ -102,6 +103,10 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
         }
         merge_partitions<T, G>(cs, lo, sh.mrg);
         ++st.rounds;
+        if (trace && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
+            trace->trace_t[st.rounds - 1] = t_round;
+            trace->trace_m[st.rounds - 1] = M;
+        }
         if (!literal) {
             uint32_t z = lo.r == 0 ? zero_hazard(cs, d) : 0u;
             uint64_t dummy = kNoKey;
@@ -125,6 +130,11 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
         st.settled += M;
     }
     write_dist(cs, lo, 0, n, dist);  // a8
+    if (trace && threadIdx.x == 0) {
+        const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
+        trace->trace_t[nr] = wall_clock64();
+        trace->trace_n = (uint32_t)nr;
+    }
 }
 
 template <int T, int G, int U>
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
     __shared__ SharedSolve<T> sh;
     SolveStats st = {0, 0, 0, 0, 0};
     const bool vec = (flags & kFlagVec) != 0;
-    solve_single<T, G, U>(W, ld, n, src, dist, pred, vec, (flags & kFlagLiteral) != 0, sh, st);
+    solve_single<T, G, U>(W, ld, n, src, dist, pred, vec, (flags & kFlagLiteral) != 0, sh, st, ctl);
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
     block_min_or<T>(dummy, s, sh.red);
@@ -152,31 +162,43 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
 // Persistent grid: one column slice per workgroup, one grid barrier per round.
 // ---------------------------------------------------------------------------
 
-// Grid barrier: arrivals counted in ctl->bar; the b-th barrier of a launch
-// completes when bar reaches b * gridDim.x.  Agent-scope release before the
-// arrival and acquire after the wait make every workgroup's published records
-// visible to all others across XCDs.  Gives up after `timeout` wall-clock
-// ticks (returns false) so that a grid that is not co-resident cannot hang.
+// Grid barrier number b (1, 2, ...) of a launch: arrivals are counted in
+// ctl->bar, and the workgroup whose arrival completes b * gridDim.x publishes
+// b in ctl->gen, which the others poll.  Every wave first waits until its
+// own stores have left the CU (s_waitcnt 0), so after the workgroup barrier
+// they all sit in this XCD's L2; one agent-scope release by thread 0 then
+// writes that L2 back before the arrival, and one agent-scope acquire after
+// the wait invalidates the CU's and XCD's caches, so the records that other
+// workgroups published (from any XCD) are read fresh.  One cache writeback and
+// one invalidate per workgroup, not per wave.  Gives up after `timeout`
+// wall-clock ticks (returns false) so that a grid that is not co-resident
+// cannot hang.
 template <int T>
-__device__ __forceinline__ bool grid_barrier(Ctl* ctl, uint32_t target, long long timeout,
-                                             SharedSolve<T>& sh) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, uint32_t b, long long timeout, SharedSolve<T>& sh) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t ok = 1;
-        __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const long long t0 = wall_clock64();
-        while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > timeout) {
-                ok = 0;
-                break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old = __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == b * gridDim.x - 1) {
+            // last arrival: every other workgroup's records were written back before
+            // its increment, which this increment observed; release barrier b
+            __hip_atomic_store(&ctl->gen, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > timeout) {
+                    ok = 0;
+                    break;
+                }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sh.flag = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return sh.flag != 0;
 }
 
@@ -200,6 +222,7 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
         ctl->status = __hip_atomic_exchange(&ctl->status_acc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->next_item, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
@@ -244,12 +267,30 @@ __device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layo
     }
 }
 
+// Entry e0 + threadIdx.x of the round's bucket, i.e. of the concatenation (in
+// workgroup order) of the lists of the records whose minimum equals d.
+// sh.pre / sh.cnt hold each record's prefix offset and count.
+template <int T>
+__device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const int32_t* __restrict__ rl,
+                                                int nwg, int S, uint32_t e0, uint32_t M) {
+    const uint32_t e = e0 + threadIdx.x;
+    if (e >= M) return 0;
+    int lo_i = 0, hi_i = nwg - 1;  // last record whose prefix is <= e (its count is non-zero)
+    while (lo_i < hi_i) {
+        const int mid = (lo_i + hi_i + 1) >> 1;
+        if (sh.pre[mid] <= e) lo_i = mid;
+        else hi_i = mid - 1;
+    }
+    return rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
+}
+
 template <int T, int G, int U>
 __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
                                             int32_t src, int32_t* __restrict__ dist,
                                             int32_t* __restrict__ pred, uint32_t flags, int32_t S,
                                             long long timeout, Ctl* __restrict__ ctl,
                                             Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
+    static_assert(T == kCap, "one staged bucket entry per thread");
     __shared__ SharedSolve<T> sh;
     SolveStats st = {0, 0, 0, 0, 0};
     const bool vec = (flags & kFlagVec) != 0;
@@ -269,7 +310,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
         for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
     uint32_t b = 0;  // barriers passed
     publish<T, G>(cand, lo, col0, 0u, &pubs[g], &lists[(int64_t)g * S], sh);
-    bool ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+    bool ok = grid_barrier<T>(ctl, ++b, timeout, sh);
 
     bool pending = false;
     uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
@@ -305,7 +346,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                 const int ns = b & 1;
                 publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
                               &lists[((size_t)ns * nwg + g) * S], sh);
-                ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+                ok = grid_barrier<T>(ctl, ++b, timeout, sh);
                 continue;
             }
             if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
@@ -316,6 +357,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
         if (K == kNoKey || d >= kInf) break;
         const uint32_t u0 = (uint32_t)K;
         ++st.rounds;
+        const long long t_round = wall_clock64();
 
         // the round's bucket: records whose local minimum equals d
         uint32_t M;
@@ -335,24 +377,22 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                 sh.cnt[threadIdx.x] = c;
             }
             __syncthreads();
+            // stage the bucket chunk by chunk; the next chunk's entries are loaded
+            // while the current chunk's rows stream
+            int32_t nxt = gather_entry<T>(sh, rl, nwg, S, 0, M);
             for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
-                const uint32_t e = e0 + threadIdx.x;
-                if (threadIdx.x < (unsigned)kCap && e < M) {
-                    // last record whose prefix is <= e (it has a non-zero count)
-                    int lo_i = 0, hi_i = nwg - 1;
-                    while (lo_i < hi_i) {
-                        const int mid = (lo_i + hi_i + 1) >> 1;
-                        if (sh.pre[mid] <= e) lo_i = mid;
-                        else hi_i = mid - 1;
-                    }
-                    sh.list[threadIdx.x] = rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
-                }
+                sh.list[threadIdx.x] = nxt;
                 __syncthreads();
+                if (e0 + kCap < M) nxt = gather_entry<T>(sh, rl, nwg, S, e0 + kCap, M);
                 stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
                 __syncthreads();
             }
         }
         merge_partitions<T, G>(cs, lo, sh.mrg);
+        if (g == 0 && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
+            ctl->trace_t[st.rounds - 1] = t_round;
+            ctl->trace_m[st.rounds - 1] = M;
+        }
 
         // would-be state if this round is applied; publish it with the hazard flag
         uint32_t neg = 0;
@@ -369,11 +409,16 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
         pu0 = u0;
         pbucket = bucket;
         pM = M;
-        ok = grid_barrier<T>(ctl, (++b) * (uint32_t)nwg, timeout, sh);
+        ok = grid_barrier<T>(ctl, ++b, timeout, sh);
     }
     if (!ok) st.status |= kStatusTimeout;
     write_dist(cs, lo, col0, width, dist);
     st.barriers = b;
+    if (g == 0 && threadIdx.x == 0) {
+        const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
+        ctl->trace_t[nr] = wall_clock64();
+        ctl->trace_n = (uint32_t)nr;
+    }
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
     block_min_or<T>(dummy, s, sh.red);
@@ -403,11 +448,11 @@ __global__ __launch_bounds__(T) void k_batch(const sssp_instance* __restrict__ i
         const bool vec = ((uintptr_t)I.W % 16 == 0) && (I.ld % 4 == 0);
         const int groups = (I.n + 3) / 4;
         if (groups <= T)
-            solve_single<T, 1, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+            solve_single<T, 1, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
         else if (groups <= 2 * T)
-            solve_single<T, 2, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+            solve_single<T, 2, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
         else
-            solve_single<T, 4, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st);
+            solve_single<T, 4, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
     }
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
@@ -443,7 +488,7 @@ int max_single_n() { return 4 * 4 * 1024; }
 
 template <int T, int G, int U>
 static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs,
-                                int32_t* lists, hipStream_t s) {
+                                int32_t* lists, bool plain, hipStream_t s) {
     const int32_t* W = a.W;
     int64_t ld = a.ld;
     int32_t n = a.n, src = a.src;
@@ -451,17 +496,22 @@ static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long ti
     int32_t* pred = a.pred;
     uint32_t flags = a.flags;
     Ctl* ctl = a.ctl;
+    if (plain) {
+        hipLaunchKernelGGL((k_grid<T, G, U>), dim3(nwg), dim3(T), 0, s, W, ld, n, src, dist, pred, flags, S,
+                           timeout, ctl, pubs, lists);
+        return hipGetLastError();
+    }
     void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &pubs, &lists};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid<T, G, U>), dim3(nwg),
                                       dim3(T), args, 0, s);
 }
 
 hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, int32_t* lists,
-                       hipStream_t s) {
+                       bool plain, hipStream_t s) {
     const int groups = (S + 3) / 4;
-    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, pubs, lists, s);
-    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, pubs, lists, s);
-    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, pubs, lists, s);
+    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
+    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
+    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
     return hipErrorInvalidValue;
 }
 

@@ -28,8 +28,11 @@ struct SolveArgs {
 hipError_t launch_single(const SolveArgs& a, int threads, hipStream_t s);
 int max_single_n();
 
+// plain: ordinary launch of the same kernel, the grid already bounded by the
+// occupancy query (co-resident on an otherwise idle GPU), instead of a
+// cooperative launch; used for profiler runs.
 hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs,
-                       int32_t* lists, hipStream_t s);
+                       int32_t* lists, bool plain, hipStream_t s);
 int max_grid_slice();
 int grid_occupancy(int slice, int* per_cu);
 

@@ -72,6 +72,9 @@ def lib():
         L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
         L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
                                                ctypes.POINTER(sssp_tuning), P]
+        L.sssp_last_trace.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), I32,
+                                      ctypes.POINTER(I32)]
+        L.sssp_last_trace.restype = ctypes.c_int
         L.sssp_batch_max_n.restype = I32
         L.sssp_single_max_n.restype = I32
         for name in ("sssp_dense_solve", "sssp_dense_solve_ex", "sssp_last_status",
@@ -130,6 +133,16 @@ def sssp_last_status(stream=None):
     stats = (ctypes.c_int64 * 4)()
     _check(lib().sssp_last_status(_stream(stream), ctypes.byref(st), stats))
     return st.value, list(stats)
+
+
+def sssp_last_trace(stream=None, cap=257):
+    """Synchronises the stream; returns [(t_ns, rows)] per round of the last solve, then (t_end, -1)."""
+    t = (ctypes.c_int64 * cap)()
+    r = (ctypes.c_int32 * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(lib().sssp_last_trace(_stream(stream), t, r, cap, ctypes.byref(cnt)))
+    k = min(cnt.value + 1, cap)
+    return [(t[i], r[i]) for i in range(k)]
 
 
 def make_instances(items):

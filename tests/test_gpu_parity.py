@@ -216,3 +216,56 @@ def test_batched_matches_alone(sp):
             total += rel
             assert np.array_equal(dist.cpu().numpy(), dr) and np.array_equal(pred.cpu().numpy(), pr)
         assert stats[1] == total
+
+
+def test_plain_launch_and_trace(sp, monkeypatch):
+    """The whole-GPU kernel through an ordinary launch gives the same result, and
+    the per-round trace lists every round with the rows it streamed."""
+    spec = gen.GraphSpec(3000, 0.05, 1, 100, 91)
+    W = gen.dense_host(spec)
+    Wt = torch.from_numpy(W).cuda()
+    monkeypatch.setenv("SSSP_GRID_LAUNCH", "plain")
+    stats = check(sp, W, 2, MODES["grid"], tag="plain", Wt=Wt)
+    tr = sp.sssp_last_trace()
+    assert len(tr) == stats[0] + 1
+    assert sum(r for _, r in tr[:-1]) == stats[1]
+    assert all(tr[i][0] <= tr[i + 1][0] for i in range(len(tr) - 1))
+    monkeypatch.delenv("SSSP_GRID_LAUNCH")
+    check(sp, W, 2, MODES["single"], tag="single-trace", Wt=Wt)
+    tr = sp.sssp_last_trace()
+    assert sum(r for _, r in tr[:-1]) == oracle.dijkstra(W, 2)[2]
+
+
+def test_barrier_timeout_is_reported_and_recovers(sp, monkeypatch):
+    """A zero wait limit makes grid barriers give up at once: the kernel still ends,
+    reports SSSP_STATUS_TIMEOUT, and the next solve is correct again."""
+    spec = gen.GraphSpec(4000, 0.05, 1, 100, 92)
+    W = gen.dense_host(spec)
+    Wt = torch.from_numpy(W).cuda()
+    monkeypatch.setenv("SSSP_BARRIER_TIMEOUT_US", "0")
+    dist, pred = sp.solve(Wt, 0, flags=MODES["grid"], workgroups=64)
+    status, _ = sp.sssp_last_status()
+    assert status & sp.SSSP_STATUS_TIMEOUT
+    monkeypatch.delenv("SSSP_BARRIER_TIMEOUT_US")
+    check(sp, W, 0, MODES["grid"], tag="after-timeout", Wt=Wt, workgroups=64)
+
+
+def test_large_workload_certificate(sp):
+    """n=65536, p=0.5, weights in [1,1000] (16 GiB), source 0, in the launch configuration the
+    benchmark times.  The serial oracle is too slow at this size, so the GPU output is checked
+    with properties that pin it exactly: the shortest-path certificate (dist is the true
+    distance, pred a shortest-path tree) and the closed-form pred, which equals Algorithm 1's
+    pred when every weight is >= 1."""
+    wl = gen.workload_single_large()
+    spec = wl.graphs[0]
+    Wt = gen.dense_device(spec)
+    Wh = gen.dense_host(spec)
+    assert gen.checksum_device(Wt) == gen.checksum_host(Wh)
+    d, p, status, stats = run(sp, Wt, 0, 0)
+    del Wt
+    torch.cuda.empty_cache()
+    assert status & 3 == 0
+    code, where = oracle.certificate(Wh, 0, d, p)
+    assert code == 0, (oracle.CERT_CODES[code], where)
+    assert np.array_equal(oracle.closed_form_pred(Wh, d), p)
+    assert stats[1] == int((d != INF).sum())
