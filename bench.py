@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--only-large", action="store_true", help="time only the n=65536 workload")
     ap.add_argument("--cpu-iters", type=int, default=32768,
                     help="iterations of the oracle timed for the CPU baseline")
+    ap.add_argument("--serve-queries", type=int, default=20000,
+                    help="queries of the served trace (Poisson arrivals at 2000/s)")
+    ap.add_argument("--plain-queries", type=int, default=2000,
+                    help="queries of the trace replayed one solve per launch for comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 4 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -85,6 +89,70 @@ def read_traffic(name):
     if m.group(1) != source_hash():
         return None
     return float(t.group(1))
+
+
+def bench_served(sp, torch, gen, args):
+    """Replays the served workload: open-loop Poisson arrivals (latency = host-observed
+    completion minus the scheduled arrival), then all queries released at once
+    (saturation throughput), then a prefix of the trace one solve per launch."""
+    wl = gen.workload_serving(n_queries=args.serve_queries)
+    mats = [gen.dense_device(g) for g in wl.graphs]
+    outs = [(torch.empty(wl.graphs[q.graph].n, dtype=torch.int32, device="cuda"),
+             torch.empty(wl.graphs[q.graph].n, dtype=torch.int32, device="cuda")) for q in wl.queries]
+    torch.cuda.synchronize()
+    res = {"graphs": len(wl.graphs), "queries": len(wl.queries), "offered_qps": 2000.0}
+    print("[bench] served: %d queries" % len(wl.queries), file=sys.stderr, flush=True)
+    with sp.Server() as srv:
+        gids = [srv.add_graph(W) for W in mats]
+        warm = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in list(zip(wl.queries, outs))[:64]]
+        for t in warm:
+            srv.wait(t, timeout_s=120)
+        srv.poll(1 << 20)
+        # open-loop replay
+        t0 = sp.sssp_server_now_ns() + 2_000_000
+        tickets = []
+        for q, (d, p) in zip(wl.queries, outs):
+            target = t0 + int(q.arrival_s * 1e9)
+            while sp.sssp_server_now_ns() < target:
+                pass
+            tickets.append(srv.submit(gids[q.graph], q.src, d, p))
+        for t in tickets:
+            srv.wait(t, timeout_s=300)
+        lat = []
+        t_end = 0
+        bad = 0
+        for q, t in zip(wl.queries, tickets):
+            inf = srv.info(t)
+            bad += inf["status"] & 3
+            lat.append((inf["t_done_ns"] - (t0 + int(q.arrival_s * 1e9))) / 1e3)
+            t_end = max(t_end, inf["t_done_ns"])
+        res["replay"] = {"p50_us": round(percentile(lat, 50), 1), "p99_us": round(percentile(lat, 99), 1),
+                         "mean_us": round(sum(lat) / len(lat), 1), "max_us": round(max(lat), 1),
+                         "solves_per_s": round(len(tickets) / ((t_end - t0) / 1e9), 1), "bad_status": bad}
+        # saturation: every query released at once
+        ts = sp.sssp_server_now_ns()
+        tickets = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in zip(wl.queries, outs)]
+        for t in tickets:
+            srv.wait(t, timeout_s=300)
+        te = max(srv.info(t)["t_done_ns"] for t in tickets)
+        rows = sum(srv.info(t)["settled"] * wl.graphs[q.graph].n for q, t in zip(wl.queries, tickets))
+        res["saturation"] = {"solves_per_s": round(len(tickets) / ((te - ts) / 1e9), 1),
+                             "seconds": round((te - ts) / 1e9, 3),
+                             "algorithmic_GBps": round(4.0 * rows / ((te - ts) / 1e9) / 1e9, 1)}
+        res["workgroups"] = srv.stats()["workgroups"]
+    # one solve per launch, synchronised each time, over a prefix of the trace
+    k = min(args.plain_queries, len(wl.queries))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, (d, p) in list(zip(wl.queries, outs))[:k]:
+        W = mats[q.graph]
+        sp.sssp_dense_solve_ex(W, W.stride(0), W.shape[0], q.src, d, p, 0)
+        torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    res["plain"] = {"queries": k, "solves_per_s": round(k / tp, 1)}
+    res["saturation_speedup_vs_plain"] = round(res["saturation"]["solves_per_s"] / (k / tp), 2)
+    del mats, outs
+    return res
 
 
 def main():
@@ -205,6 +273,10 @@ def main():
                             "speedup_vs_plain": round(tp / tb, 3), "status": status,
                             "rows_relaxed": bstats[1]}
         del mats, items
+        torch.cuda.empty_cache()
+
+        # ---- served: 32 resident graphs, Poisson trace, continuous batching --------
+        extra["served"] = bench_served(sp, torch, gen, args)
         torch.cuda.empty_cache()
 
     # ---- CPU oracle on a bounded sample of the headline workload -----------------

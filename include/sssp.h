@@ -129,6 +129,89 @@ int32_t sssp_batch_max_n(void);
 /* Largest n the one-workgroup kernel accepts. */
 int32_t sssp_single_max_n(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of (graph, source) queries on a persistent
+ * kernel.  Graphs stay resident in HBM; each query is solved exactly as
+ * sssp_dense_solve would solve it (same dist and pred).  A query is solved by
+ * one workgroup when n <= single_max_n, otherwise by a gang of workgroups
+ * that split its columns (the column division of Section III-B inside the
+ * running kernel).  Submitted queries wait in a FIFO until a query slot, ring
+ * space and (for gangs) arena memory for their exchange records are free,
+ * then run concurrently with those already on the GPU.  While queries are
+ * pending or running the server's kernel stays resident on the compute units
+ * it was given (all but a few by default; other kernels run on the rest), so a
+ * device-wide synchronisation (hipDeviceSynchronize) returns only after the
+ * server has been idle for idle_park_ms and its kernel has left; prefer
+ * stream synchronisation.  Buffers passed to submit must already hold their
+ * final contents on the device (no pending writes).
+ * ---------------------------------------------------------------------- */
+typedef struct sssp_server sssp_server;
+
+typedef struct sssp_server_config {
+    int32_t workgroups;     /* persistent workgroups (0 = one per CU, leaving max(4, CUs/32) CUs free) */
+    int32_t ring_slots;     /* descriptor ring entries (0 = 4096) */
+    int32_t max_inflight;   /* queries admitted to the GPU at once (0 = 1024) */
+    int32_t single_max_n;   /* largest n solved by one workgroup (0 = 4096; at most 16384) */
+    int32_t gang_columns;   /* columns per gang member for larger n (0 = 2048; multiple of 4) */
+    int32_t watchdog_ms;    /* kernel leaves if the host heartbeat stalls this long (0 = 2000) */
+    int64_t scratch_bytes;  /* device arena for gang exchange records (0 = 256 MiB) */
+    int64_t max_pending;    /* submissions waiting for admission before SSSP_EAGAIN (0 = no limit) */
+    int32_t idle_park_ms;   /* kernel leaves after this long with no query; relaunched on demand (0 = 20) */
+    int32_t reserved[7];
+} sssp_server_config;
+
+/* query states */
+#define SSSP_QUERY_PENDING 0
+#define SSSP_QUERY_RUNNING 1
+#define SSSP_QUERY_DONE 2
+
+typedef struct sssp_query_info {
+    int32_t state;        /* SSSP_QUERY_* */
+    int32_t status;       /* SSSP_STATUS_* bits of its solve */
+    int32_t parts;        /* workgroups that solved it */
+    int32_t rounds;
+    int64_t settled;      /* rows relaxed */
+    int64_t t_submit_ns;  /* sssp_server_now_ns() clock */
+    int64_t t_admit_ns;
+    int64_t t_done_ns;    /* when the host saw the completion record */
+} sssp_query_info;
+
+typedef struct sssp_server_stats {
+    int64_t submitted, completed, running, pending, kernel_launches;
+    int32_t workgroups;
+    int32_t failed;  /* a relaunch of the kernel failed */
+} sssp_server_stats;
+
+/* Host monotonic clock (ns) used for all server timestamps. */
+int64_t sssp_server_now_ns(void);
+
+/* Creates a server on the current device and launches its kernel; cfg may be NULL. */
+int sssp_server_create(const sssp_server_config* cfg, sssp_server** out);
+
+/* Registers a device-resident n x n matrix (row stride ld); the server borrows
+ * W until sssp_server_destroy.  *graph_id receives its id. */
+int sssp_server_add_graph(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, int32_t* graph_id);
+
+/* Queues a query; dist and pred are caller-owned device buffers of n int32
+ * that must stay valid until the query is done.  Never blocks; returns
+ * SSSP_EAGAIN when max_pending queries already wait, SSSP_ENOGRAPH for an
+ * unknown graph.  *ticket (1, 2, ...) names the query. */
+int sssp_server_submit(sssp_server* s, int32_t graph_id, int32_t src, int32_t* dist, int32_t* pred,
+                       uint64_t* ticket);
+
+/* Moves up to cap tickets of completed, not yet polled queries into tickets[]. */
+int sssp_server_poll(sssp_server* s, uint64_t* tickets, int32_t cap, int32_t* count);
+
+/* Waits until the query is done (timeout_ns < 0: no limit); SSSP_ETIMEDOUT otherwise.
+ * dist/pred are then complete in device memory. */
+int sssp_server_wait(sssp_server* s, uint64_t ticket, int64_t timeout_ns);
+
+int sssp_server_query_info(sssp_server* s, uint64_t ticket, sssp_query_info* info);
+int sssp_server_get_stats(sssp_server* s, sssp_server_stats* stats);
+
+/* Drains (every submitted query completes), stops the kernel, frees the server. */
+int sssp_server_destroy(sssp_server* s);
+
 #ifdef __cplusplus
 }
 #endif

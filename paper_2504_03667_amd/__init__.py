@@ -3,13 +3,18 @@
 The compute path is libsssp.so (HIP kernels behind the C ABI in include/sssp.h);
 this package only binds it.  See sssp.py.
 """
-from .sssp import (INF, SSSP_FLAG_GRID, SSSP_FLAG_LITERAL, SSSP_FLAG_SINGLE, SSSP_STAT_BARRIERS,
+from .sssp import (Server, SSSP_QUERY_DONE, sssp_server_add_graph, sssp_server_create,
+                   sssp_server_destroy, sssp_server_get_stats, sssp_server_now_ns, sssp_server_poll,
+                   sssp_server_query_info, sssp_server_submit, sssp_server_wait,
+                   INF, SSSP_FLAG_GRID, SSSP_FLAG_LITERAL, SSSP_FLAG_SINGLE, SSSP_STAT_BARRIERS,
                    SSSP_STAT_FALLBACKS, SSSP_STAT_ROUNDS, SSSP_STAT_SETTLED,
                    SSSP_STATUS_NEG_WEIGHT, SSSP_STATUS_TIMEOUT, SSSP_STATUS_ZERO_FALLBACK,
                    SsspError, lib, solve, sssp_dense_solve, sssp_dense_solve_batched,
                    sssp_dense_solve_ex, sssp_last_status, sssp_last_trace)
 
-__all__ = ["INF", "SSSP_FLAG_GRID", "SSSP_FLAG_LITERAL", "SSSP_FLAG_SINGLE", "SSSP_STAT_BARRIERS",
+__all__ = ["Server", "SSSP_QUERY_DONE", "sssp_server_add_graph", "sssp_server_create",
+           "sssp_server_destroy", "sssp_server_get_stats", "sssp_server_now_ns", "sssp_server_poll",
+           "sssp_server_query_info", "sssp_server_submit", "sssp_server_wait", "INF", "SSSP_FLAG_GRID", "SSSP_FLAG_LITERAL", "SSSP_FLAG_SINGLE", "SSSP_STAT_BARRIERS",
            "SSSP_STAT_FALLBACKS", "SSSP_STAT_ROUNDS", "SSSP_STAT_SETTLED",
            "SSSP_STATUS_NEG_WEIGHT", "SSSP_STATUS_TIMEOUT", "SSSP_STATUS_ZERO_FALLBACK",
            "SsspError", "lib", "solve", "sssp_dense_solve", "sssp_dense_solve_batched",

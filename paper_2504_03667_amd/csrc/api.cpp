@@ -288,6 +288,13 @@ int batched(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp
 }
 
 }  // namespace
+
+// Records an error message for sssp_last_error() (used by server.cpp).
+int set_error(int code, const char* msg) {
+    t_err = msg;
+    return code;
+}
+
 }  // namespace sssp
 
 using namespace sssp;

@@ -44,20 +44,29 @@ enum { kStatRounds = 0, kStatSettled = 1, kStatFallbacks = 2, kStatBarriers = 3,
 
 constexpr int kTraceCap = 256;  // rounds recorded per launch (round start time, bucket size)
 
+// Barrier words of one group of workgroups (the whole grid, or a gang of a
+// served query).  The arrival counter, the release word that waiters poll and
+// the exit counter sit on separate 128-byte lines so that polling does not
+// contend with arrivals.  All zero between uses: the last member to leave
+// resets them.
+struct Bar {
+    uint32_t bar;  // arrivals
+    uint32_t pad0[31];
+    uint32_t gen;  // number of the last completed barrier
+    uint32_t pad1[31];
+    uint32_t exit;  // members that have left
+    uint32_t pad2[31];
+};
+
 // Per-launch control block in device memory.  Zeroed once when allocated;
 // every launch leaves it ready for the next (the last workgroup to finish
-// resets the barrier words and moves the accumulators into `last`).  The
-// arrival counter and the release word the waiters poll sit on separate
-// 128-byte lines so that polling does not contend with the arrivals.
+// resets the barrier words and moves the accumulators into `last`).
 struct Ctl {
-    uint32_t bar;  // grid-barrier arrivals in the current launch
-    uint32_t pad0[31];
-    uint32_t gen;  // number of the last completed grid barrier of the current launch
-    uint32_t pad1[31];
-    uint32_t exit;        // workgroups that finished the current launch
+    Bar b;
     uint32_t status_acc;  // status bits OR-ed during the current launch
     uint32_t status;      // status of the last finished launch
     uint32_t trace_n;     // rounds recorded in trace_t / trace_m by the last launch
+    uint32_t pad;
     unsigned long long acc[kStatCount];
     unsigned long long last[kStatCount];
     unsigned long long next_item;  // work-queue ticket counter (batched kernels)

@@ -159,35 +159,37 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
 }
 
 // ---------------------------------------------------------------------------
-// Persistent grid: one column slice per workgroup, one grid barrier per round.
+// Gang solve: `nwg` workgroups (ranks 0..nwg-1) each own a column slice of S
+// columns and meet at one barrier per round.  Used by the whole-GPU kernel
+// (the gang is the grid) and by the serving kernel (a gang per large query).
 // ---------------------------------------------------------------------------
 
-// Grid barrier number b (1, 2, ...) of a launch: arrivals are counted in
-// ctl->bar, and the workgroup whose arrival completes b * gridDim.x publishes
-// b in ctl->gen, which the others poll.  Every wave first waits until its
-// own stores have left the CU (s_waitcnt 0), so after the workgroup barrier
-// they all sit in this XCD's L2; one agent-scope release by thread 0 then
-// writes that L2 back before the arrival, and one agent-scope acquire after
-// the wait invalidates the CU's and XCD's caches, so the records that other
-// workgroups published (from any XCD) are read fresh.  One cache writeback and
-// one invalidate per workgroup, not per wave.  Gives up after `timeout`
-// wall-clock ticks (returns false) so that a grid that is not co-resident
-// cannot hang.
+// Barrier number b (1, 2, ...) of a gang of `members` workgroups: arrivals are
+// counted in bw->bar, and the member whose arrival completes b * members
+// publishes b in bw->gen, which the others poll.  Every wave first waits until
+// its own stores have left the CU (s_waitcnt 0), so after the workgroup barrier
+// they all sit in this XCD's L2; one agent-scope release by thread 0 then writes
+// that L2 back before the arrival, and one agent-scope acquire after the wait
+// invalidates the CU's and XCD's caches, so records that other members
+// published (from any XCD) are read fresh.  One cache writeback and one
+// invalidate per workgroup, not per wave.  Gives up after `timeout` wall-clock
+// ticks (returns false) so that a gang that is not co-resident cannot hang.
 template <int T>
-__device__ __forceinline__ bool grid_barrier(Ctl* ctl, uint32_t b, long long timeout, SharedSolve<T>& sh) {
+__device__ __forceinline__ bool gang_barrier(Bar* bw, uint32_t b, uint32_t members, long long timeout,
+                                             SharedSolve<T>& sh) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t ok = 1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t old = __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b * gridDim.x - 1) {
-            // last arrival: every other workgroup's records were written back before
+        const uint32_t old = __hip_atomic_fetch_add(&bw->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == b * members - 1) {
+            // last arrival: every other member's records were written back before
             // its increment, which this increment observed; release barrier b
-            __hip_atomic_store(&ctl->gen, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bw->gen, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) {
+            while (__hip_atomic_load(&bw->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > timeout) {
                     ok = 0;
@@ -202,7 +204,19 @@ __device__ __forceinline__ bool grid_barrier(Ctl* ctl, uint32_t b, long long tim
     return sh.flag != 0;
 }
 
-// The last workgroup to finish publishes the launch's statistics and resets
+// Thread 0 of each member calls this once when it is done with the gang's
+// words; the last of `members` resets them for the next use.  Returns true in
+// the last member.
+__device__ __forceinline__ bool gang_leave(Bar* bw, uint32_t members) {
+    const uint32_t prev = __hip_atomic_fetch_add(&bw->exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev != members - 1) return false;
+    __hip_atomic_store(&bw->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&bw->gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&bw->exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// The last workgroup of a launch publishes the launch's statistics and resets
 // the barrier words, the ticket counter and the accumulators for the next launch.
 __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bool add_stats) {
     if (threadIdx.x != 0) return;
@@ -213,7 +227,7 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
         __hip_atomic_fetch_add(&ctl->acc[kStatFallbacks], st.fallbacks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&ctl->acc[kStatBarriers], st.barriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint32_t prev = __hip_atomic_fetch_add(&ctl->exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t prev = __hip_atomic_fetch_add(&ctl->b.exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == gridDim.x - 1) {
         for (int i = 0; i < kStatCount; ++i) {
             ctl->last[i] = __hip_atomic_load(&ctl->acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -221,9 +235,9 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
         }
         ctl->status = __hip_atomic_exchange(&ctl->status_acc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->next_item, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->b.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->b.gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->b.exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -284,18 +298,15 @@ __device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const 
     return rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
 }
 
+// Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
+// entries (double-buffered by barrier parity).  Returns false if a barrier
+// wait timed out.  `trace` (may be null) receives rank 0's round trace.
 template <int T, int G, int U>
-__global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
-                                            int32_t src, int32_t* __restrict__ dist,
-                                            int32_t* __restrict__ pred, uint32_t flags, int32_t S,
-                                            long long timeout, Ctl* __restrict__ ctl,
-                                            Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
+__device__ bool solve_gang(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
+                           int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
+                           int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
+                           int32_t* __restrict__ lists, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
     static_assert(T == kCap, "one staged bucket entry per thread");
-    __shared__ SharedSolve<T> sh;
-    SolveStats st = {0, 0, 0, 0, 0};
-    const bool vec = (flags & kFlagVec) != 0;
-    const bool literal = (flags & kFlagLiteral) != 0;
-    const int nwg = gridDim.x, g = blockIdx.x;
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
     const Layout lo = make_layout<T>(S);
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
         for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
     uint32_t b = 0;  // barriers passed
     publish<T, G>(cand, lo, col0, 0u, &pubs[g], &lists[(int64_t)g * S], sh);
-    bool ok = grid_barrier<T>(ctl, ++b, timeout, sh);
+    bool ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
 
     bool pending = false;
     uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
@@ -346,7 +357,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                 const int ns = b & 1;
                 publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
                               &lists[((size_t)ns * nwg + g) * S], sh);
-                ok = grid_barrier<T>(ctl, ++b, timeout, sh);
+                ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
                 continue;
             }
             if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
@@ -389,9 +400,9 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
             }
         }
         merge_partitions<T, G>(cs, lo, sh.mrg);
-        if (g == 0 && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
-            ctl->trace_t[st.rounds - 1] = t_round;
-            ctl->trace_m[st.rounds - 1] = M;
+        if (trace && g == 0 && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
+            trace->trace_t[st.rounds - 1] = t_round;
+            trace->trace_m[st.rounds - 1] = M;
         }
 
         // would-be state if this round is applied; publish it with the hazard flag
@@ -409,21 +420,34 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
         pu0 = u0;
         pbucket = bucket;
         pM = M;
-        ok = grid_barrier<T>(ctl, ++b, timeout, sh);
+        ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
     }
     if (!ok) st.status |= kStatusTimeout;
     write_dist(cs, lo, col0, width, dist);
-    st.barriers = b;
-    if (g == 0 && threadIdx.x == 0) {
+    st.barriers += b;
+    if (trace && g == 0 && threadIdx.x == 0) {
         const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
-        ctl->trace_t[nr] = wall_clock64();
-        ctl->trace_n = (uint32_t)nr;
+        trace->trace_t[nr] = wall_clock64();
+        trace->trace_n = (uint32_t)nr;
     }
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
     block_min_or<T>(dummy, s, sh.red);
     st.status = s;
-    finish_launch(ctl, st, g == 0);
+    return ok;
+}
+
+template <int T, int G, int U>
+__global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
+                                            int32_t src, int32_t* __restrict__ dist,
+                                            int32_t* __restrict__ pred, uint32_t flags, int32_t S,
+                                            long long timeout, Ctl* __restrict__ ctl,
+                                            Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
+    __shared__ SharedSolve<T> sh;
+    SolveStats st = {0, 0, 0, 0, 0};
+    solve_gang<T, G, U>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
+                        blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl);
+    finish_launch(ctl, st, blockIdx.x == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -459,6 +483,125 @@ __global__ __launch_bounds__(T) void k_batch(const sssp_instance* __restrict__ i
     block_min_or<T>(dummy, s, sh.red);
     st.status = s;
     finish_launch(ctl, st, true);
+}
+
+// ---------------------------------------------------------------------------
+// Serving: a persistent grid whose workgroups claim query parts from a ring
+// that the host fills in pinned memory.  A query with parts == 1 is solved by
+// the claiming workgroup alone (k_single's engine); a larger one is split into
+// `parts` column slices claimed by as many workgroups, which form a gang with
+// its own barrier words (k_grid's engine).  Gang members claim consecutive
+// ring entries, so at most the newest gang is incomplete at any time and it
+// completes as soon as enough workgroups are free: parts <= gridDim.x keeps
+// this deadlock-free.
+// ---------------------------------------------------------------------------
+
+// Claim the next published ring entry (copied into *out) or decide to leave:
+// returns true to leave (nothing published and the host set stop or park, or
+// the host's heartbeat stalled for `watchdog` ticks).  The host publishes
+// nothing while park is set, so no gang can be left half claimed.  Ring and control words live in
+// host memory that the host writes while the kernel runs, so they are read
+// with system-scope atomic loads (never through the scalar cache).
+__device__ __forceinline__ bool serve_claim(const ServeArgs& a, ServeDesc* out) {
+    unsigned long long hb = __hip_atomic_load(&a.ctl->heartbeat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    long long hb_t = wall_clock64();
+    unsigned naps = 1;
+    for (unsigned poll = 0;; ++poll) {
+        const unsigned long long t = __hip_atomic_load(&a.ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        unsigned long long h = __hip_atomic_load(a.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < t) {
+            if (__hip_atomic_compare_exchange_strong(a.head, &h, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                const unsigned long long* src =
+                    reinterpret_cast<const unsigned long long*>(&a.ring[h % (unsigned long long)a.ring_slots]);
+                unsigned long long* dst = reinterpret_cast<unsigned long long*>(out);
+                for (unsigned i = 0; i < sizeof(ServeDesc) / 8; ++i)
+                    dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                return false;
+            }
+            naps = 1;
+            continue;
+        }
+        if ((poll & 15) == 0) {
+            if (__hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ||
+                __hip_atomic_load(&a.ctl->park, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                return true;
+            const unsigned long long hb2 =
+                __hip_atomic_load(&a.ctl->heartbeat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            const long long now = wall_clock64();
+            if (hb2 != hb) {
+                hb = hb2;
+                hb_t = now;
+            } else if (now - hb_t > a.watchdog) {
+                return true;
+            }
+        }
+        for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
+        if (naps < 4) naps <<= 1;
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_serve(ServeArgs a) {
+    __shared__ SharedSolve<T> sh;
+    __shared__ ServeDesc q;
+    __shared__ int32_t leave;
+    for (;;) {
+        if (threadIdx.x == 0) leave = serve_claim(a, &q) ? 1 : 0;
+        __syncthreads();
+        if (leave) break;
+        SolveStats st = {0, 0, 0, 0, 0};
+        const bool vec = ((uintptr_t)q.W % 16 == 0) && (q.ld % 4 == 0);
+        if (q.parts <= 1) {
+            const int groups = (q.n + 3) / 4;
+            if (groups <= T)
+                solve_single<T, 1, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
+            else if (groups <= 2 * T)
+                solve_single<T, 2, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
+            else
+                solve_single<T, 4, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
+            uint32_t s = st.status;
+            uint64_t dummy = kNoKey;
+            block_min_or<T>(dummy, s, sh.red);
+            st.status = s;
+        } else {
+            Pub* pubs = reinterpret_cast<Pub*>(a.arena + q.scratch_off);
+            int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * q.parts);
+            Bar* bw = &a.bars[q.qslot];
+            const int groups = (q.S + 3) / 4;
+            if (groups <= T)
+                solve_gang<T, 1, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
+                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
+            else if (groups <= 2 * T)
+                solve_gang<T, 2, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
+                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
+            else
+                solve_gang<T, 4, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
+                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
+            if (threadIdx.x == 0) gang_leave(bw, (uint32_t)q.parts);
+        }
+        // completion: the last part to finish writes the slot's record to host memory
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ServeSlot* sl = &a.slots[q.qslot];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (st.status) __hip_atomic_fetch_or(&sl->status, st.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t prev = __hip_atomic_fetch_add(&sl->done_parts, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == (uint32_t)q.parts - 1) {
+                const uint32_t status = __hip_atomic_exchange(&sl->status, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sl->done_parts, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ServeDone* dn = &a.done[q.qslot];
+                __hip_atomic_store(&dn->status, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&dn->rounds, (uint32_t)st.rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&dn->settled, st.settled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(&dn->t_done, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                // every part's dist/pred writes are in memory before the host sees the ticket
+                __hip_atomic_store(&dn->ticket, q.ticket, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -542,9 +685,23 @@ int batch_occupancy(int threads, int* per_cu) {
 
 int max_batch_n(int threads) { return 4 * 4 * (threads <= 256 ? 256 : 1024); }
 
+hipError_t launch_serve(const ServeArgs& a, int nwg, hipStream_t s) {
+    hipLaunchKernelGGL((k_serve<1024>), dim3(nwg), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+int serve_occupancy(int* per_cu) {
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(&k_serve<1024>),
+                                                             1024, 0);
+}
+
+int max_serve_single_n() { return 4 * 4 * 1024; }
+int max_serve_slice() { return 4 * 4 * 1024; }
+
 }  // namespace sssp
 
 namespace sssp {
 size_t ctl_size() { return sizeof(Ctl); }
 size_t pub_size() { return sizeof(Pub); }
+size_t bar_size() { return sizeof(Bar); }
 }  // namespace sssp

@@ -9,6 +9,7 @@ namespace sssp {
 
 struct Ctl;
 struct Pub;
+struct Bar;
 
 // internal flag bits, above the public SSSP_FLAG_* bits
 constexpr uint32_t kFlagLiteral = SSSP_FLAG_LITERAL;
@@ -43,5 +44,77 @@ int max_batch_n(int threads);
 
 size_t ctl_size();
 size_t pub_size();
+
+}  // namespace sssp
+
+// ---------------------------------------------------------------------------
+// Serving: structures shared by the persistent kernel and the host server.
+// ---------------------------------------------------------------------------
+namespace sssp {
+
+// Host-written control words, in fine-grained (coherent) pinned host memory.
+struct ServeControl {
+    unsigned long long tail;  // ring entries published so far
+    unsigned long long pad0[15];
+    unsigned long long heartbeat;  // bumped by the host server thread while it lives
+    unsigned long long pad1[15];
+    uint32_t stop;  // set once: workgroups leave when they find no work
+    uint32_t park;  // set while the host has nothing in flight: idle workgroups leave
+    uint32_t pad2[30];
+};
+
+// One part of a query: rank `part` of a gang of `parts` workgroups (parts == 1:
+// the query is solved by one workgroup alone).  Written by the host into the
+// ring (pinned host memory) before `tail` is advanced past it.
+struct ServeDesc {
+    const int32_t* W;
+    int64_t ld;
+    int32_t* dist;
+    int32_t* pred;
+    int32_t n;
+    int32_t src;
+    int32_t part;
+    int32_t parts;
+    int32_t S;               // columns per gang member
+    uint32_t qslot;          // in-flight query slot (device state, completion record)
+    unsigned long long ticket;
+    unsigned long long scratch_off;  // byte offset of the gang's records and lists in the arena
+};
+
+// Completion record of a query slot, written by the GPU into pinned host memory.
+struct ServeDone {
+    unsigned long long ticket;  // ticket of the query that completed in this slot
+    uint32_t status;
+    uint32_t rounds;
+    unsigned long long settled;
+    long long t_done;  // device wall clock at completion
+    unsigned long long pad[4];
+};
+
+// Per-slot device state of an in-flight query.
+struct ServeSlot {
+    uint32_t done_parts;  // gang members finished
+    uint32_t status;      // status bits OR-ed by the members
+    uint32_t pad[30];
+};
+
+struct ServeArgs {
+    ServeControl* ctl;         // pinned
+    const ServeDesc* ring;     // pinned
+    int32_t ring_slots;
+    ServeDone* done;           // pinned, one per query slot
+    ServeSlot* slots;          // device, one per query slot
+    Bar* bars;                 // device, one per query slot
+    unsigned long long* head;  // device: ring entries claimed so far
+    char* arena;               // device scratch for gang records and lists
+    long long timeout;         // gang barrier wait limit (wall-clock ticks)
+    long long watchdog;        // leave when the heartbeat stalls this long (ticks)
+};
+
+hipError_t launch_serve(const ServeArgs& a, int nwg, hipStream_t s);
+int serve_occupancy(int* per_cu);
+int max_serve_single_n();
+int max_serve_slice();
+size_t bar_size();
 
 }  // namespace sssp

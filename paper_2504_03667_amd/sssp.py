@@ -51,6 +51,29 @@ class sssp_instance(ctypes.Structure):
                 ("src", ctypes.c_int32), ("dist", ctypes.c_void_p), ("pred", ctypes.c_void_p)]
 
 
+class sssp_server_config(ctypes.Structure):
+    _fields_ = [("workgroups", ctypes.c_int32), ("ring_slots", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("single_max_n", ctypes.c_int32),
+                ("gang_columns", ctypes.c_int32), ("watchdog_ms", ctypes.c_int32),
+                ("scratch_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int64),
+                ("idle_park_ms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class sssp_query_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("parts", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("settled", ctypes.c_int64),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class sssp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("pending", ctypes.c_int64), ("kernel_launches", ctypes.c_int64),
+                ("workgroups", ctypes.c_int32), ("failed", ctypes.c_int32)]
+
+
+SSSP_QUERY_PENDING, SSSP_QUERY_RUNNING, SSSP_QUERY_DONE = 0, 1, 2
+
 _lib = None
 
 
@@ -77,8 +100,19 @@ def lib():
         L.sssp_last_trace.restype = ctypes.c_int
         L.sssp_batch_max_n.restype = I32
         L.sssp_single_max_n.restype = I32
+        L.sssp_server_now_ns.restype = I64
+        L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
+        L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
+        L.sssp_server_submit.argtypes = [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.sssp_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), I32, ctypes.POINTER(I32)]
+        L.sssp_server_wait.argtypes = [P, ctypes.c_uint64, I64]
+        L.sssp_server_query_info.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(sssp_query_info)]
+        L.sssp_server_get_stats.argtypes = [P, ctypes.POINTER(sssp_server_stats)]
+        L.sssp_server_destroy.argtypes = [P]
         for name in ("sssp_dense_solve", "sssp_dense_solve_ex", "sssp_last_status",
-                     "sssp_dense_solve_batched"):
+                     "sssp_dense_solve_batched", "sssp_server_create", "sssp_server_add_graph",
+                     "sssp_server_submit", "sssp_server_poll", "sssp_server_wait",
+                     "sssp_server_query_info", "sssp_server_get_stats", "sssp_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -178,3 +212,106 @@ def solve(W, src, flags=0, threads=0, workgroups=0, stream=None):
     pred = torch.empty(n, dtype=torch.int32, device=W.device)
     sssp_dense_solve_ex(W, W.stride(0), n, src, dist, pred, flags, threads, workgroups, stream)
     return dist, pred
+
+
+# ---- serving (sssp_server_*) ----
+
+def sssp_server_now_ns():
+    return lib().sssp_server_now_ns()
+
+
+def sssp_server_create(**cfg):
+    c = sssp_server_config()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    _check(lib().sssp_server_create(ctypes.byref(c), ctypes.byref(h)))
+    return h
+
+
+def sssp_server_add_graph(h, W, ld, n):
+    gid = ctypes.c_int32(-1)
+    _check(lib().sssp_server_add_graph(h, _ptr(W, "W"), ld, n, ctypes.byref(gid)))
+    return gid.value
+
+
+def sssp_server_submit(h, graph_id, src, dist, pred):
+    t = ctypes.c_uint64(0)
+    _check(lib().sssp_server_submit(h, graph_id, src, _ptr(dist, "dist"), _ptr(pred, "pred"),
+                                    ctypes.byref(t)))
+    return t.value
+
+
+def sssp_server_poll(h, cap=4096):
+    buf = (ctypes.c_uint64 * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(lib().sssp_server_poll(h, buf, cap, ctypes.byref(cnt)))
+    return list(buf[:cnt.value])
+
+
+def sssp_server_wait(h, ticket, timeout_s=None):
+    ns = -1 if timeout_s is None else int(timeout_s * 1e9)
+    return _check(lib().sssp_server_wait(h, ticket, ns))
+
+
+def sssp_server_query_info(h, ticket):
+    i = sssp_query_info()
+    _check(lib().sssp_server_query_info(h, ticket, ctypes.byref(i)))
+    return {k: getattr(i, k) for k, _ in sssp_query_info._fields_}
+
+
+def sssp_server_get_stats(h):
+    s = sssp_server_stats()
+    _check(lib().sssp_server_get_stats(h, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in sssp_server_stats._fields_}
+
+
+def sssp_server_destroy(h):
+    return _check(lib().sssp_server_destroy(h))
+
+
+class Server:
+    """Owns an sssp_server and keeps the tensors it borrows alive while it needs them."""
+
+    def __init__(self, **cfg):
+        self.h = sssp_server_create(**cfg)
+        self._graphs = []
+        self._outs = {}
+
+    def add_graph(self, W):
+        gid = sssp_server_add_graph(self.h, W, W.stride(0), W.shape[0])
+        self._graphs.append(W)
+        return gid
+
+    def submit(self, graph_id, src, dist, pred):
+        t = sssp_server_submit(self.h, graph_id, src, dist, pred)
+        self._outs[t] = (dist, pred)
+        return t
+
+    def poll(self, cap=4096):
+        done = sssp_server_poll(self.h, cap)
+        for t in done:
+            self._outs.pop(t, None)
+        return done
+
+    def wait(self, ticket, timeout_s=None):
+        sssp_server_wait(self.h, ticket, timeout_s)
+
+    def info(self, ticket):
+        return sssp_server_query_info(self.h, ticket)
+
+    def stats(self):
+        return sssp_server_get_stats(self.h)
+
+    def close(self):
+        if self.h is not None:
+            sssp_server_destroy(self.h)
+            self.h = None
+            self._outs.clear()
+            self._graphs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,164 @@
+"""GPU tests of the serving path (persistent kernel + host admission): every served
+query must equal the oracle and its own solve alone, whatever else runs beside it."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests.graphs import random_dense
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_03667_amd as m
+    m.lib()
+    return m
+
+
+def make_graphs(rng, sizes):
+    out = []
+    for i, n in enumerate(sizes):
+        W = random_dense(rng, n, float(rng.choice([0.003, 0.02, 0.2])), 1, 1000, directed=bool(i % 3 == 0),
+                         zero_prob=0.02 if i == 2 else 0.0)
+        out.append(W)
+    return out
+
+
+def outputs(n):
+    d = torch.full((n,), -9, dtype=torch.int32, device="cuda")
+    p = torch.full((n,), -9, dtype=torch.int32, device="cuda")
+    # the fill must land before the server writes results; synchronise the stream,
+    # not the device (a device-wide sync would also wait for the serving kernel)
+    torch.cuda.current_stream().synchronize()
+    return d, p
+
+
+def test_server_matches_oracle_with_gangs(sp):
+    """Small single_max_n / gang_columns force multi-workgroup gangs on modest n."""
+    rng = np.random.default_rng(200)
+    graphs = make_graphs(rng, [5, 300, 700, 1500, 2100, 3333])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    plan = []
+    for k in range(60):
+        g = int(rng.integers(0, len(graphs)))
+        plan.append((g, int(rng.integers(0, graphs[g].shape[0])), *outputs(graphs[g].shape[0])))
+    with sp.Server(single_max_n=512, gang_columns=256) as srv:
+        gids = [srv.add_graph(W) for W in dev]
+        jobs = [(g, src, d, p, srv.submit(gids[g], src, d, p)) for g, src, d, p in plan]
+        for g, src, d, p, t in jobs:
+            srv.wait(t, timeout_s=60)
+            info = srv.info(t)
+            dr, pr, rel = oracle.dijkstra(graphs[g], src)
+            assert info["state"] == sp.SSSP_QUERY_DONE and info["status"] & 3 == 0
+            assert info["settled"] == rel
+            n = graphs[g].shape[0]
+            assert info["parts"] == (1 if n <= 512 else info["parts"]) and (n <= 512 or info["parts"] > 1)
+            assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), (g, src)
+        st = srv.stats()
+        assert st["completed"] == 60 and st["running"] == 0 and st["pending"] == 0
+        assert sorted(srv.poll()) == [j[4] for j in jobs]
+
+
+def test_server_alone_equals_mix(sp):
+    """Each query's result alone (submitted and awaited one at a time) equals its result in
+    a burst where it overlaps with all the others, and equals sssp_dense_solve."""
+    rng = np.random.default_rng(201)
+    graphs = make_graphs(rng, [900, 2500, 5000, 6000])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    qs = [(int(g), int(rng.integers(0, graphs[g].shape[0]))) for g in rng.integers(0, 4, size=40)]
+    outs_alone = [outputs(graphs[g].shape[0]) for g, _ in qs]
+    outs_mix = [outputs(graphs[g].shape[0]) for g, _ in qs]
+    with sp.Server(single_max_n=4096, gang_columns=1024) as srv:
+        gids = [srv.add_graph(W) for W in dev]
+        alone = []
+        for (g, src), (d, p) in zip(qs, outs_alone):
+            srv.wait(srv.submit(gids[g], src, d, p), timeout_s=60)
+            alone.append((d.cpu().numpy(), p.cpu().numpy()))
+        mix = []
+        for (g, src), (d, p) in zip(qs, outs_mix):
+            mix.append((srv.submit(gids[g], src, d, p), d, p))
+        for (t, d, p), (da, pa) in zip(mix, alone):
+            srv.wait(t, timeout_s=60)
+            assert np.array_equal(d.cpu().numpy(), da) and np.array_equal(p.cpu().numpy(), pa)
+    for (g, src), (da, pa) in zip(qs, alone):
+        d, p = sp.solve(dev[g], src)
+        assert np.array_equal(d.cpu().numpy(), da) and np.array_equal(p.cpu().numpy(), pa)
+
+
+def test_server_memory_admission(sp):
+    """An arena that holds one gang's exchange records at a time: queries wait for memory
+    instead of failing, and every one completes correctly."""
+    rng = np.random.default_rng(202)
+    graphs = make_graphs(rng, [3000, 3100])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    # footprint of a 3100-vertex gang with 256 columns per member: 13 members
+    big = torch.from_numpy(random_dense(rng, 8000, 0.01, 1, 9)).cuda()
+    bd, bp = outputs(8000)
+    plan = [(k % 2, int(rng.integers(0, graphs[k % 2].shape[0])), *outputs(graphs[k % 2].shape[0]))
+            for k in range(12)]
+    with sp.Server(single_max_n=256, gang_columns=256, scratch_bytes=60000) as srv:
+        gids = [srv.add_graph(W) for W in dev]
+        jobs = [(g, src, d, p, srv.submit(gids[g], src, d, p)) for g, src, d, p in plan]
+        saw_wait = srv.stats()["pending"] > 0
+        for g, src, d, p, t in jobs:
+            srv.wait(t, timeout_s=60)
+            dr, pr, _ = oracle.dijkstra(graphs[g], src)
+            assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr)
+        assert saw_wait
+        gb = srv.add_graph(big)
+        with pytest.raises(sp.SsspError) as e:
+            srv.submit(gb, 0, bd, bp)  # its gang records alone exceed the arena
+        assert e.value.code == -3  # SSSP_ENOMEM
+
+
+def test_server_errors_and_backpressure(sp):
+    rng = np.random.default_rng(203)
+    W = torch.from_numpy(random_dense(rng, 2000, 0.5, 1, 9)).cuda()
+    d, p = outputs(2000)
+    outs = [outputs(2000) for _ in range(30)]
+    with sp.Server(max_pending=1, max_inflight=1) as srv:
+        gid = srv.add_graph(W)
+        with pytest.raises(sp.SsspError) as e:
+            srv.submit(gid + 5, 0, d, p)
+        assert e.value.code == -5  # SSSP_ENOGRAPH
+        with pytest.raises(sp.SsspError) as e:
+            srv.submit(gid, 2000, d, p)
+        assert e.value.code == -1
+        tickets, again = [], 0
+        for d, p in outs:
+            try:
+                tickets.append(srv.submit(gid, 0, d, p))
+            except sp.SsspError as ex:
+                assert ex.code == -4  # SSSP_EAGAIN
+                again += 1
+        assert again > 0 and tickets
+        for t in tickets:
+            srv.wait(t, timeout_s=60)
+    dr, pr, _ = oracle.dijkstra(W.cpu().numpy(), 0)
+    assert np.array_equal(outs[0][0].cpu().numpy(), dr)
+
+
+def test_server_workload_sample(sp):
+    """A sample of the served workload's graphs (n up to 32768) and queries."""
+    wl = gen.workload_serving(n_queries=64)
+    pick = sorted({q.graph for q in wl.queries})[:8]
+    host = {g: gen.dense_host(wl.graphs[g]) for g in pick}
+    dev = {g: torch.from_numpy(host[g]).cuda() for g in pick}
+    qs = [q for q in wl.queries if q.graph in pick]
+    outs = [outputs(wl.graphs[q.graph].n) for q in qs]
+    with sp.Server() as srv:
+        gids = {g: srv.add_graph(dev[g]) for g in pick}
+        jobs = [(q, d, p, srv.submit(gids[q.graph], q.src, d, p)) for q, (d, p) in zip(qs, outs)]
+        for q, d, p, t in jobs:
+            srv.wait(t, timeout_s=120)
+            W = host[q.graph]
+            dd, pp = d.cpu().numpy(), p.cpu().numpy()
+            code, where = oracle.certificate(W, q.src, dd, pp)
+            assert code == 0, (q, oracle.CERT_CODES[code], where)
+            assert np.array_equal(oracle.closed_form_pred(W, dd), pp)
