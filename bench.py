@@ -18,6 +18,8 @@ import re
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -91,6 +93,60 @@ def read_traffic(name):
     return float(t.group(1))
 
 
+def median_launch_ms(torch, fn, reps=7):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2] * 1e3
+
+
+def bench_batched(sp, torch, gen):
+    """256 sources on one n=8192 graph plus 64 graphs: one-shot launch, autotuned plans
+    (int32 and exact compact copies, replayed as a hipGraph) and one solve per launch."""
+    wl = gen.workload_batched()
+    mats = [gen.dense_device(g) for g in wl.graphs]
+    items = []
+    for gi, src in wl.instances:
+        nn = wl.graphs[gi].n
+        items.append((mats[gi], src, torch.empty(nn, dtype=torch.int32, device="cuda"),
+                      torch.empty(nn, dtype=torch.int32, device="cuda")))
+    res = {"instances": len(items)}
+    t_one = median_launch_ms(torch, lambda: sp.sssp_dense_solve_batched(items))
+    status, bstats = sp.sssp_last_status()
+    res["one_shot"] = {"launch_ms": round(t_one, 3), "solves_per_s": round(len(items) / t_one * 1e3, 1),
+                       "status": status}
+    ref = [(d.cpu().numpy().copy(), p.cpu().numpy().copy()) for _, _, d, p in items]
+    for name, flags in (("plan_int32", 0), ("plan_compact", sp.SSSP_FLAG_COMPACT)):
+        with sp.BatchPlan(items, flags) as plan:
+            t = median_launch_ms(torch, plan.launch)
+            st, _ = plan.status()
+            info = plan.info()
+            same = all(np.array_equal(d.cpu().numpy(), a) and np.array_equal(p.cpu().numpy(), b)
+                       for (_, _, d, p), (a, b) in zip(items, ref))
+        res[name] = {"launch_ms": round(t, 3), "solves_per_s": round(len(items) / t * 1e3, 1), "status": st,
+                     "identical_to_one_shot": same, "single_max_n": info["single_max_n"],
+                     "gang_columns": info["gang_columns"], "candidates": info["candidates"],
+                     "compact_graphs": info["compact_graphs"], "build_ms": round(info["build_ms"], 1)}
+    # plain path: one sssp_dense_solve per instance, synchronised each time
+    t0 = time.perf_counter()
+    for W_, src, dist_, pred_ in items:
+        sp.sssp_dense_solve_ex(W_, W_.stride(0), W_.shape[0], src, dist_, pred_, 0)
+        torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    plain = len(items) / tp
+    res["plain_solves_per_s"] = round(plain, 1)
+    res["rows_relaxed"] = bstats[1]
+    for name in ("one_shot", "plan_int32", "plan_compact"):
+        res[name]["speedup_vs_plain"] = round(res[name]["solves_per_s"] / plain, 2)
+    del mats, items
+    return res
+
+
 def bench_served(sp, torch, gen, args):
     """Replays the served workload: open-loop Poisson arrivals (latency = host-observed
     completion minus the scheduled arrival), then all queries released at once
@@ -101,45 +157,50 @@ def bench_served(sp, torch, gen, args):
              torch.empty(wl.graphs[q.graph].n, dtype=torch.int32, device="cuda")) for q in wl.queries]
     torch.cuda.synchronize()
     res = {"graphs": len(wl.graphs), "queries": len(wl.queries), "offered_qps": 2000.0}
-    print("[bench] served: %d queries" % len(wl.queries), file=sys.stderr, flush=True)
-    with sp.Server() as srv:
-        gids = [srv.add_graph(W) for W in mats]
-        warm = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in list(zip(wl.queries, outs))[:64]]
-        for t in warm:
-            srv.wait(t, timeout_s=120)
-        srv.poll(1 << 20)
-        # open-loop replay
-        t0 = sp.sssp_server_now_ns() + 2_000_000
-        tickets = []
-        for q, (d, p) in zip(wl.queries, outs):
-            target = t0 + int(q.arrival_s * 1e9)
-            while sp.sssp_server_now_ns() < target:
-                pass
-            tickets.append(srv.submit(gids[q.graph], q.src, d, p))
-        for t in tickets:
-            srv.wait(t, timeout_s=300)
-        lat = []
-        t_end = 0
-        bad = 0
-        for q, t in zip(wl.queries, tickets):
-            inf = srv.info(t)
-            bad += inf["status"] & 3
-            lat.append((inf["t_done_ns"] - (t0 + int(q.arrival_s * 1e9))) / 1e3)
-            t_end = max(t_end, inf["t_done_ns"])
-        res["replay"] = {"p50_us": round(percentile(lat, 50), 1), "p99_us": round(percentile(lat, 99), 1),
-                         "mean_us": round(sum(lat) / len(lat), 1), "max_us": round(max(lat), 1),
-                         "solves_per_s": round(len(tickets) / ((t_end - t0) / 1e9), 1), "bad_status": bad}
-        # saturation: every query released at once
-        ts = sp.sssp_server_now_ns()
-        tickets = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in zip(wl.queries, outs)]
-        for t in tickets:
-            srv.wait(t, timeout_s=300)
-        te = max(srv.info(t)["t_done_ns"] for t in tickets)
-        rows = sum(srv.info(t)["settled"] * wl.graphs[q.graph].n for q, t in zip(wl.queries, tickets))
-        res["saturation"] = {"solves_per_s": round(len(tickets) / ((te - ts) / 1e9), 1),
-                             "seconds": round((te - ts) / 1e9, 3),
-                             "algorithmic_GBps": round(4.0 * rows / ((te - ts) / 1e9) / 1e9, 1)}
-        res["workgroups"] = srv.stats()["workgroups"]
+    for name, flags, replay in (("server_int32", 0, False), ("server_compact", sp.SSSP_FLAG_COMPACT, True)):
+        print("[bench] served %s: %d queries" % (name, len(wl.queries)), file=sys.stderr, flush=True)
+        r = {}
+        with sp.Server() as srv:
+            gids = [srv.add_graph(W, flags) for W in mats]
+            r["graphs_compact"] = sum(1 for g in gids if srv.graph_elem(g) < 4)
+            warm = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in list(zip(wl.queries, outs))[:64]]
+            for t in warm:
+                srv.wait(t, timeout_s=120)
+            srv.poll(1 << 20)
+            if replay:
+                # open-loop replay: latency = host-observed completion - scheduled arrival
+                t0 = sp.sssp_server_now_ns() + 2_000_000
+                tickets = []
+                for q, (d, p) in zip(wl.queries, outs):
+                    target = t0 + int(q.arrival_s * 1e9)
+                    while sp.sssp_server_now_ns() < target:
+                        pass
+                    tickets.append(srv.submit(gids[q.graph], q.src, d, p))
+                for t in tickets:
+                    srv.wait(t, timeout_s=300)
+                lat, t_end, bad = [], 0, 0
+                for q, t in zip(wl.queries, tickets):
+                    inf = srv.info(t)
+                    bad += inf["status"] & 3
+                    lat.append((inf["t_done_ns"] - (t0 + int(q.arrival_s * 1e9))) / 1e3)
+                    t_end = max(t_end, inf["t_done_ns"])
+                r["replay"] = {"p50_us": round(percentile(lat, 50), 1), "p99_us": round(percentile(lat, 99), 1),
+                               "mean_us": round(sum(lat) / len(lat), 1), "max_us": round(max(lat), 1),
+                               "solves_per_s": round(len(tickets) / ((t_end - t0) / 1e9), 1), "bad_status": bad}
+            # saturation: every query released at once
+            ts = sp.sssp_server_now_ns()
+            tickets = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in zip(wl.queries, outs)]
+            for t in tickets:
+                srv.wait(t, timeout_s=300)
+            infos = [srv.info(t) for t in tickets]
+            te = max(i["t_done_ns"] for i in infos)
+            rows = sum(i["settled"] * wl.graphs[q.graph].n for q, i in zip(wl.queries, infos))
+            r["saturation"] = {"solves_per_s": round(len(tickets) / ((te - ts) / 1e9), 1),
+                               "seconds": round((te - ts) / 1e9, 3),
+                               "bad_status": sum(i["status"] & 3 for i in infos),
+                               "algorithmic_GBps": round(4.0 * rows / ((te - ts) / 1e9) / 1e9, 1)}
+            r["workgroups"] = srv.stats()["workgroups"]
+        res[name] = r
     # one solve per launch, synchronised each time, over a prefix of the trace
     k = min(args.plain_queries, len(wl.queries))
     torch.cuda.synchronize()
@@ -150,7 +211,8 @@ def bench_served(sp, torch, gen, args):
         torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     res["plain"] = {"queries": k, "solves_per_s": round(k / tp, 1)}
-    res["saturation_speedup_vs_plain"] = round(res["saturation"]["solves_per_s"] / (k / tp), 2)
+    for name in ("server_int32", "server_compact"):
+        res[name]["saturation_speedup_vs_plain"] = round(res[name]["saturation"]["solves_per_s"] / (k / tp), 2)
     del mats, outs
     return res
 
@@ -162,7 +224,6 @@ def main():
               "single MI355X (--gpus %d requested). Multi-GPU column sharding is described in "
               "DESIGN.md and not implemented." % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import gen
@@ -243,36 +304,7 @@ def main():
         del W1
 
         # ---- batched: 320 instances in one launch vs one solve per launch ---------
-        wl4 = gen.workload_batched()
-        mats = [gen.dense_device(g) for g in wl4.graphs]
-        items = []
-        for gi, src in wl4.instances:
-            nn = wl4.graphs[gi].n
-            items.append((mats[gi], src, torch.empty(nn, dtype=torch.int32, device="cuda"),
-                          torch.empty(nn, dtype=torch.int32, device="cuda")))
-        for _ in range(2):
-            sp.sssp_dense_solve_batched(items)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(5):
-            t0 = time.perf_counter()
-            sp.sssp_dense_solve_batched(items)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        status, bstats = sp.sssp_last_status()
-        tb = sorted(times)[len(times) // 2]
-        # plain path: one sssp_dense_solve per instance, synchronised each time
-        t0 = time.perf_counter()
-        for W_, src, dist_, pred_ in items:
-            sp.sssp_dense_solve_ex(W_, W_.stride(0), W_.shape[0], src, dist_, pred_, 0)
-            torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        extra["batched"] = {"instances": len(items), "launch_ms": round(tb * 1e3, 3),
-                            "solves_per_s": round(len(items) / tb, 1),
-                            "plain_solves_per_s": round(len(items) / tp, 1),
-                            "speedup_vs_plain": round(tp / tb, 3), "status": status,
-                            "rows_relaxed": bstats[1]}
-        del mats, items
+        extra["batched"] = bench_batched(sp, torch, gen)
         torch.cuda.empty_cache()
 
         # ---- served: 32 resident graphs, Poisson trace, continuous batching --------

@@ -59,6 +59,8 @@ extern "C" {
 #define SSSP_FLAG_LITERAL 1u  /* settle one vertex per round: Algorithm 1 exactly as printed */
 #define SSSP_FLAG_SINGLE 2u   /* force the one-workgroup kernel */
 #define SSSP_FLAG_GRID 4u     /* force the persistent whole-GPU kernel */
+#define SSSP_FLAG_COMPACT 8u  /* plans and servers: stream an exact uint8/uint16 copy of each graph
+                                 whose weights all fit (built once, owned by the plan or server) */
 
 /* statistics of a finished launch (sssp_last_status `stats`, 4 entries) */
 #define SSSP_STAT_ROUNDS 0     /* rounds (one bucket of equal-dist vertices, or one vertex, each) */
@@ -68,9 +70,11 @@ extern "C" {
 
 /* Tuning knobs; pass NULL for the library's choice.  A zero field means "choose". */
 typedef struct sssp_tuning {
-    int32_t threads;     /* workgroup size: 256 or 1024 */
-    int32_t workgroups;  /* workgroups of the whole-GPU kernel, or of a batched launch */
-    int32_t reserved[6];
+    int32_t threads;       /* one-workgroup solve: workgroup size, 256 or 1024 */
+    int32_t workgroups;    /* workgroups of the whole-GPU kernel, or of a batched launch */
+    int32_t single_max_n;  /* batched plans: largest n solved by one workgroup (0 = autotune) */
+    int32_t gang_columns;  /* batched plans: columns per gang member above that */
+    int32_t reserved[4];
 } sssp_tuning;
 
 /* One solve of a batch: same meaning as the arguments of sssp_dense_solve_ex. */
@@ -119,12 +123,55 @@ int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int
 /*
  * Batched solve: `count` independent instances (host array of descriptors
  * pointing at device buffers; instances may share W) in ONE persistent launch
- * in which each workgroup pulls instances from a ticket counter and solves
- * each one alone, largest first.  Every instance needs n <= sssp_batch_max_n().
+ * in which workgroups pull work from a ticket counter, largest instance first:
+ * an instance with n <= sssp_batch_max_n() is solved by one workgroup, a
+ * larger one by a gang of workgroups that split its columns.  Asynchronous.
  */
 int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags,
                              const sssp_tuning* tuning, void* stream);
 int32_t sssp_batch_max_n(void);
+
+/*
+ * Batched plans: built once for a fixed set of instances, launched many times.
+ * Creation (synchronous on `stream`) validates the instances; with
+ * SSSP_FLAG_COMPACT it builds exact compact copies of the distinct matrices
+ * whose weights fit (uint8 when 0 <= w <= 254, uint16 when <= 65534; the
+ * all-ones code means "no edge"), which cut the bytes streamed per row 4x or
+ * 2x and give identical dist/pred; it then measures candidate splits of the
+ * instances into workgroups (one workgroup per instance, or gangs of
+ * workgroups that share an instance's columns) unless `tuning` fixes one,
+ * keeps the fastest, and captures the launch into a hipGraph.  A launch
+ * replays the graph on `stream`: one persistent kernel for all instances.
+ * The instance buffers must stay valid while the plan exists.
+ */
+typedef struct sssp_batch_plan sssp_batch_plan;
+
+typedef struct sssp_plan_info {
+    int32_t threads, workgroups;
+    int32_t single_max_n, gang_columns;  /* the chosen split */
+    int32_t max_parts;                   /* largest gang */
+    int32_t candidates;                  /* configurations measured */
+    int32_t compact_graphs;              /* matrices streamed from a compact copy */
+    int32_t graph;                       /* 1: launches replay a captured hipGraph */
+    int64_t compact_bytes;               /* device bytes held by the compact copies */
+    double tuned_ms;                     /* time of the chosen configuration, -1 if not measured */
+    double build_ms;                     /* wall time of sssp_batch_plan_create */
+} sssp_plan_info;
+
+int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
+                           void* stream, sssp_batch_plan** out);
+int sssp_batch_plan_launch(sssp_batch_plan* plan, void* stream);
+int sssp_batch_plan_info(const sssp_batch_plan* plan, sssp_plan_info* info);
+/* Synchronises `stream`; status and SSSP_STAT_* counters of the plan's last launch. */
+int sssp_batch_plan_status(sssp_batch_plan* plan, void* stream, int32_t* status, int64_t* stats);
+/* Waits for the plan's last launch, then frees it and its compact copies. */
+int sssp_batch_plan_destroy(sssp_batch_plan* plan);
+
+/* Weight range of a device matrix (synchronous): *min_w over all entries, *max_finite_w
+ * over entries other than INT32_MAX.  *min_w < 0 means the input violates Dijkstra's
+ * precondition. */
+int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w, int32_t* max_finite_w,
+                        void* stream);
 
 /* Largest n the one-workgroup kernel accepts. */
 int32_t sssp_single_max_n(void);
@@ -191,6 +238,15 @@ int sssp_server_create(const sssp_server_config* cfg, sssp_server** out);
 /* Registers a device-resident n x n matrix (row stride ld); the server borrows
  * W until sssp_server_destroy.  *graph_id receives its id. */
 int sssp_server_add_graph(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, int32_t* graph_id);
+
+/* As sssp_server_add_graph; with SSSP_FLAG_COMPACT the server builds and keeps an
+ * exact uint8/uint16 copy of W when its weights fit (see sssp_batch_plan_create)
+ * and streams that copy.  Synchronous. */
+int sssp_server_add_graph_ex(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, uint32_t flags,
+                             int32_t* graph_id);
+
+/* Bytes per matrix entry the server streams for a graph: 4, 2 or 1. */
+int sssp_server_graph_elem(sssp_server* s, int32_t graph_id, int32_t* elem_bytes);
 
 /* Queues a query; dist and pred are caller-owned device buffers of n int32
  * that must stay valid until the query is done.  Never blocks; returns

@@ -3,7 +3,10 @@
 The compute path is libsssp.so (HIP kernels behind the C ABI in include/sssp.h);
 this package only binds it.  See sssp.py.
 """
-from .sssp import (Server, SSSP_QUERY_DONE, sssp_server_add_graph, sssp_server_create,
+from .sssp import (BatchPlan, SSSP_FLAG_COMPACT, sssp_batch_max_n, sssp_batch_plan_create,
+                   sssp_batch_plan_destroy, sssp_batch_plan_info, sssp_batch_plan_launch,
+                   sssp_batch_plan_status, sssp_dense_validate, sssp_server_add_graph_ex,
+                   sssp_server_graph_elem, Server, SSSP_QUERY_DONE, sssp_server_add_graph, sssp_server_create,
                    sssp_server_destroy, sssp_server_get_stats, sssp_server_now_ns, sssp_server_poll,
                    sssp_server_query_info, sssp_server_submit, sssp_server_wait,
                    INF, SSSP_FLAG_GRID, SSSP_FLAG_LITERAL, SSSP_FLAG_SINGLE, SSSP_STAT_BARRIERS,
@@ -12,7 +15,10 @@ from .sssp import (Server, SSSP_QUERY_DONE, sssp_server_add_graph, sssp_server_c
                    SsspError, lib, solve, sssp_dense_solve, sssp_dense_solve_batched,
                    sssp_dense_solve_ex, sssp_last_status, sssp_last_trace)
 
-__all__ = ["Server", "SSSP_QUERY_DONE", "sssp_server_add_graph", "sssp_server_create",
+__all__ = ["BatchPlan", "SSSP_FLAG_COMPACT", "sssp_batch_max_n", "sssp_batch_plan_create",
+           "sssp_batch_plan_destroy", "sssp_batch_plan_info", "sssp_batch_plan_launch",
+           "sssp_batch_plan_status", "sssp_dense_validate", "sssp_server_add_graph_ex",
+           "sssp_server_graph_elem", "Server", "SSSP_QUERY_DONE", "sssp_server_add_graph", "sssp_server_create",
            "sssp_server_destroy", "sssp_server_get_stats", "sssp_server_now_ns", "sssp_server_poll",
            "sssp_server_query_info", "sssp_server_submit", "sssp_server_wait", "INF", "SSSP_FLAG_GRID", "SSSP_FLAG_LITERAL", "SSSP_FLAG_SINGLE", "SSSP_STAT_BARRIERS",
            "SSSP_STAT_FALLBACKS", "SSSP_STAT_ROUNDS", "SSSP_STAT_SETTLED",

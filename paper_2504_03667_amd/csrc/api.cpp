@@ -48,12 +48,6 @@ struct Scratch {
     size_t pubs_cap = 0;
     int32_t* lists = nullptr;
     size_t lists_cap = 0;
-    sssp_instance* inst = nullptr;  // device copy of a batch
-    int32_t* order = nullptr;
-    size_t inst_cap = 0;
-    sssp_instance* inst_h = nullptr;  // pinned staging
-    int32_t* order_h = nullptr;
-    hipEvent_t staged = nullptr;
     bool launched = false;
 };
 
@@ -215,84 +209,35 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
     return SSSP_OK;
 }
 
-// Device instance array + pinned host staging for batched launches.
-int stage_capacity(Scratch* sc, size_t count) {
-    if (sc->staged) {
-        hipError_t e = hipEventSynchronize(sc->staged);  // previous upload done with the staging area
-        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    } else if (hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming) != hipSuccess) {
-        return fail(SSSP_EDEVICE, "hipEventCreate");
-    }
-    if (count <= sc->inst_cap) return SSSP_OK;
-    hipError_t e = hipStreamSynchronize(sc->stream);  // an earlier launch may still read the arrays
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    (void)hipFree(sc->inst);
-    (void)hipFree(sc->order);
-    (void)hipHostFree(sc->inst_h);
-    (void)hipHostFree(sc->order_h);
-    sc->inst = nullptr;
-    sc->order = nullptr;
-    sc->inst_h = nullptr;
-    sc->order_h = nullptr;
-    sc->inst_cap = 0;
-    const size_t cap = std::max<size_t>(count, 64);
-    if (hipMalloc(&sc->inst, sizeof(sssp_instance) * cap) != hipSuccess ||
-        hipMalloc(&sc->order, sizeof(int32_t) * cap) != hipSuccess ||
-        hipHostMalloc(&sc->inst_h, sizeof(sssp_instance) * cap) != hipSuccess ||
-        hipHostMalloc(&sc->order_h, sizeof(int32_t) * cap) != hipSuccess)
-        return fail(SSSP_ENOMEM, "allocating the batch instance arrays (%zu entries)", cap);
-    sc->inst_cap = cap;
-    return SSSP_OK;
+}  // namespace
+
+// Records an error message for sssp_last_error() (used by the other sources).
+int set_error(int code, const char* msg) {
+    t_err = msg;
+    return code;
 }
 
-int batched(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
-            hipStream_t stream) {
-    if (count < 0 || (count > 0 && !inst)) return fail(SSSP_EINVAL, "bad instance array");
-    if (count == 0) return SSSP_OK;
-    int threads = tuning && tuning->threads ? tuning->threads : 0;
-    int32_t nmax = 0;
-    for (int32_t i = 0; i < count; ++i) {
-        const sssp_instance& I = inst[i];
-        int rc = check_solve_args(I.W, I.ld, I.n, I.src, I.dist, I.pred);
-        if (rc) return fail(rc, "instance %d: %s", i, t_err.c_str());
-        nmax = std::max(nmax, I.n);
-    }
-    if (!threads) threads = nmax <= max_batch_n(256) ? 256 : 1024;
-    if (nmax > max_batch_n(threads))
-        return fail(SSSP_EUNSUPPORTED, "instance n=%d exceeds the batched limit %d", nmax, max_batch_n(threads));
+const char* last_error_text() { return t_err.c_str(); }
+
+// Control block of (current device, stream), marked as used by a launch that
+// the caller is about to enqueue; its stats are what sssp_last_status reports.
+int stream_ctl(hipStream_t stream, Ctl** out, int* cus, long long* clock_khz) {
     std::lock_guard<std::mutex> lk(g_mu);
     Scratch* sc = nullptr;
     DeviceInfo di;
     int rc = get_scratch(stream, &sc, &di);
     if (rc) return rc;
-    rc = stage_capacity(sc, (size_t)count);
-    if (rc) return rc;
-    memcpy(sc->inst_h, inst, sizeof(sssp_instance) * count);
-    for (int32_t i = 0; i < count; ++i) sc->order_h[i] = i;
-    std::stable_sort(sc->order_h, sc->order_h + count,
-                     [&](int32_t x, int32_t y) { return inst[x].n > inst[y].n; });  // largest first
-    hipError_t e = hipMemcpyAsync(sc->inst, sc->inst_h, sizeof(sssp_instance) * count, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sc->order, sc->order_h, sizeof(int32_t) * count, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipEventRecord(sc->staged, stream);
-    if (e != hipSuccess) return hip_fail(e, "staging the instance array");
-    int per_cu = 0;
-    e = (hipError_t)batch_occupancy(threads, &per_cu);
-    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-    int nwg = tuning && tuning->workgroups ? tuning->workgroups : per_cu * di.cus;
-    nwg = std::max(1, std::min(nwg, count));
-    e = launch_batch(sc->inst, count, sc->order, flags & SSSP_FLAG_LITERAL, sc->ctl, threads, nwg, stream);
-    if (e != hipSuccess) return hip_fail(e, "launch(batched solve)");
     sc->launched = true;
+    *out = sc->ctl;
+    if (cus) *cus = di.cus;
+    if (clock_khz) *clock_khz = di.clock_khz;
     return SSSP_OK;
 }
 
-}  // namespace
-
-// Records an error message for sssp_last_error() (used by server.cpp).
-int set_error(int code, const char* msg) {
-    t_err = msg;
-    return code;
+int check_instance(const sssp_instance& I, int idx) {
+    int rc = check_solve_args(I.W, I.ld, I.n, I.src, I.dist, I.pred);
+    if (rc) return fail(rc, "instance %d: %s", idx, t_err.c_str());
+    return SSSP_OK;
 }
 
 }  // namespace sssp
@@ -373,12 +318,6 @@ int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int
     return SSSP_OK;
 }
 
-int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags,
-                             const sssp_tuning* tuning, void* stream) {
-    return batched(inst, count, flags, tuning, (hipStream_t)stream);
-}
-
-int32_t sssp_batch_max_n(void) { return max_batch_n(1024); }
 
 int32_t sssp_single_max_n(void) { return max_single_n(); }
 

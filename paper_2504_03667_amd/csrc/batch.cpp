@@ -1,0 +1,458 @@
+// Batched solves: the one-shot call, and plans that are built once (exact
+// compact copies of reused graphs, autotuned workgroups per instance, one
+// captured hipGraph) and launched many times.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "engine.h"
+#include "sssp_internal.h"
+
+namespace sssp {
+int set_error(int code, const char* msg);
+const char* last_error_text();
+int stream_ctl(hipStream_t stream, Ctl** out, int* cus, long long* clock_khz);
+int check_instance(const sssp_instance& I, int idx);
+}  // namespace sssp
+
+using namespace sssp;
+
+namespace {
+
+int err(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return set_error(code, buf);
+}
+
+int hip_err(hipError_t e, const char* what) { return err(SSSP_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+// The matrix an instance is streamed from: the caller's, or a compact copy.
+struct Source {
+    const void* W;
+    int64_t ld;
+    int elem;
+};
+
+struct Build {
+    std::vector<BatchItem> items;  // largest first
+    std::vector<BatchPart> parts;
+    uint64_t arena_bytes = 0;
+    int32_t max_parts = 1;
+};
+
+bool aligned(const void* p, int64_t ld, int elem) {
+    return ((uintptr_t)p % (4 * (uintptr_t)elem)) == 0 && ld % 4 == 0;
+}
+
+// Items in largest-first order; an instance with n > single_max_n is split
+// into parts of at most gang_columns columns solved by a gang of workgroups.
+int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t single_max_n,
+          int32_t gang_columns, int32_t max_parts, Build* out) {
+    std::vector<int32_t> order(count);
+    for (int32_t i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return inst[x].n > inst[y].n; });
+    out->items.clear();
+    out->parts.clear();
+    out->arena_bytes = 0;
+    out->max_parts = 1;
+    for (int32_t k = 0; k < count; ++k) {
+        const sssp_instance& I = inst[order[k]];
+        BatchItem b;
+        memset(&b, 0, sizeof b);
+        b.W = src[order[k]].W;
+        b.ld = src[order[k]].ld;
+        b.elem = src[order[k]].elem;
+        b.dist = I.dist;
+        b.pred = I.pred;
+        b.n = I.n;
+        b.src = I.src;
+        b.vec = aligned(b.W, b.ld, b.elem) ? 1 : 0;
+        if (I.n <= single_max_n) {
+            b.parts = 1;
+            b.S = I.n;
+        } else {
+            int64_t p = ((int64_t)I.n + gang_columns - 1) / gang_columns;
+            p = std::max<int64_t>(2, std::min<int64_t>(p, max_parts));
+            int64_t s = ((int64_t)I.n + p - 1) / p;
+            s = (s + 3) & ~int64_t(3);
+            if (s > max_batch_slice())
+                return err(SSSP_EUNSUPPORTED, "instance n=%d needs more than %d workgroups", I.n, max_parts);
+            b.S = (int32_t)s;
+            b.parts = (int32_t)(((int64_t)I.n + s - 1) / s);
+            b.scratch_off = out->arena_bytes;
+            const uint64_t bytes = 2ull * b.parts * pub_size() + 2ull * b.parts * (uint64_t)b.S * 4;
+            out->arena_bytes += (bytes + 255) & ~uint64_t(255);
+            out->max_parts = std::max(out->max_parts, b.parts);
+        }
+        for (int32_t j = 0; j < b.parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
+        out->items.push_back(b);
+    }
+    return SSSP_OK;
+}
+
+int check_all(const sssp_instance* inst, int32_t count) {
+    if (count < 0 || (count > 0 && !inst)) return err(SSSP_EINVAL, "bad instance array");
+    for (int32_t i = 0; i < count; ++i) {
+        int rc = check_instance(inst[i], i);
+        if (rc) return rc;
+    }
+    return SSSP_OK;
+}
+
+}  // namespace
+
+namespace sssp {
+
+// Exact compact copy of W when every weight is >= 0 and every finite weight
+// fits below the all-ones code of uint8 (<= 254) or uint16 (<= 65534).
+// Synchronous.  out->elem == 4 (and no copy) when neither fits.
+int make_compact(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, CompactCopy* out) {
+    out->data = nullptr;
+    out->ld = ld;
+    out->elem = 4;
+    int32_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, 2 * sizeof(int32_t));
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc(range): %s", hipGetErrorString(e));
+    int32_t init[2] = {0x7fffffff, (int32_t)0x80000000}, r[2];
+    e = hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = weight_range(W, ld, n, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, d, sizeof r, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_err(e, "weight range");
+    out->wmin = r[0];
+    out->wmax = r[1];
+    int elem = 4;
+    if (r[0] >= 0 && r[1] <= 254) elem = 1;
+    else if (r[0] >= 0 && r[1] <= 65534) elem = 2;
+    if (elem == 4) return SSSP_OK;
+    const int64_t ldc = ((int64_t)n + 15) & ~int64_t(15);
+    void* c = nullptr;
+    e = hipMalloc(&c, (size_t)ldc * n * elem);
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc(compact copy): %s", hipGetErrorString(e));
+    e = compact_copy(W, ld, n, c, ldc, elem, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(c);
+        return hip_err(e, "compact copy");
+    }
+    out->data = c;
+    out->ld = ldc;
+    out->elem = elem;
+    return SSSP_OK;
+}
+
+}  // namespace sssp
+
+struct sssp_batch_plan {
+    int device = 0;
+    uint32_t flags = 0;
+    int nwg = 0;
+    long long clock_khz = 100000;
+    std::vector<sssp_instance> inst;
+    std::vector<Source> src;
+    std::vector<CompactCopy> copies;
+    BatchItem* d_items = nullptr;
+    BatchPart* d_parts = nullptr;
+    int32_t nparts = 0;
+    Bar* d_bars = nullptr;
+    char* d_arena = nullptr;
+    Ctl* d_ctl = nullptr;
+    hipStream_t cap = nullptr;
+    hipEvent_t done = nullptr;  // recorded after every launch of the graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    sssp_plan_info info{};
+
+    void free_device() {
+        (void)hipFree(d_items);
+        (void)hipFree(d_parts);
+        (void)hipFree(d_bars);
+        (void)hipFree(d_arena);
+        d_items = nullptr;
+        d_parts = nullptr;
+        d_bars = nullptr;
+        d_arena = nullptr;
+    }
+
+    // Upload one configuration's items, parts and scratch.
+    int upload(int32_t single_max_n, int32_t gang_columns) {
+        Build b;
+        int rc = ::build(inst.data(), src.data(), (int32_t)inst.size(), single_max_n, gang_columns,
+                         std::max(2, nwg / 2), &b);
+        if (rc) return rc;
+        free_device();
+        hipError_t e = hipMalloc(&d_items, sizeof(BatchItem) * b.items.size());
+        if (e == hipSuccess) e = hipMalloc(&d_parts, sizeof(BatchPart) * b.parts.size());
+        if (e == hipSuccess) e = hipMalloc(&d_bars, sizeof(Bar) * b.items.size());
+        if (e == hipSuccess && b.arena_bytes) e = hipMalloc(&d_arena, b.arena_bytes);
+        if (e != hipSuccess) return err(SSSP_ENOMEM, "allocating a batch plan: %s", hipGetErrorString(e));
+        e = hipMemcpy(d_items, b.items.data(), sizeof(BatchItem) * b.items.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_parts, b.parts.data(), sizeof(BatchPart) * b.parts.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(d_bars, 0, sizeof(Bar) * b.items.size());
+        if (e != hipSuccess) return hip_err(e, "uploading a batch plan");
+        nparts = (int32_t)b.parts.size();
+        info.max_parts = b.max_parts;
+        return SSSP_OK;
+    }
+
+    hipError_t enqueue(hipStream_t s) {
+        return launch_batch(d_items, d_parts, nparts, d_bars, d_arena, flags & SSSP_FLAG_LITERAL,
+                            clock_khz * 10000, d_ctl, nwg, s);
+    }
+};
+
+extern "C" {
+
+int32_t sssp_batch_max_n(void) { return max_batch_single_n(); }
+
+int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w, int32_t* max_finite_w,
+                        void* stream) {
+    if (!W || !min_w || !max_finite_w) return err(SSSP_EINVAL, "null argument");
+    if (n < 1 || ld < n) return err(SSSP_EINVAL, "need n >= 1 and ld >= n");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, 2 * sizeof(int32_t));
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    int32_t init[2] = {0x7fffffff, (int32_t)0x80000000}, r[2];
+    e = hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = weight_range(W, ld, n, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, d, sizeof r, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_err(e, "weight range");
+    *min_w = r[0];
+    *max_finite_w = r[1];
+    return SSSP_OK;
+}
+
+int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
+                             void* stream) {
+    int rc = check_all(inst, count);
+    if (rc) return rc;
+    if (count == 0) return SSSP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Ctl* ctl = nullptr;
+    int cus = 0;
+    long long khz = 100000;
+    rc = stream_ctl(s, &ctl, &cus, &khz);
+    if (rc) return rc;
+    int per_cu = 0;
+    if (batch_occupancy(&per_cu) != 0 || per_cu < 1) return err(SSSP_EDEVICE, "batched kernel does not fit a CU");
+    int nwg = tuning && tuning->workgroups ? std::min(tuning->workgroups, per_cu * cus) : per_cu * cus;
+    std::vector<Source> src(count);
+    for (int32_t i = 0; i < count; ++i) src[i] = Source{inst[i].W, inst[i].ld, 4};
+    Build b;
+    rc = build(inst, src.data(), count, max_batch_single_n(), 4096, std::max(2, nwg / 2), &b);
+    if (rc) return rc;
+    nwg = std::max(1, std::min<int>(nwg, (int)b.parts.size()));
+    if (nwg < b.max_parts) nwg = b.max_parts;
+    // stream-ordered scratch: allocated and freed in the stream's order, so the
+    // call stays asynchronous (copies from pageable memory are staged at once)
+    BatchItem* d_items = nullptr;
+    BatchPart* d_parts = nullptr;
+    Bar* d_bars = nullptr;
+    char* d_arena = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d_items, sizeof(BatchItem) * b.items.size(), s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&d_parts, sizeof(BatchPart) * b.parts.size(), s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&d_bars, sizeof(Bar) * b.items.size(), s);
+    if (e == hipSuccess && b.arena_bytes) e = hipMallocAsync((void**)&d_arena, b.arena_bytes, s);
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync(batch): %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d_items, b.items.data(), sizeof(BatchItem) * b.items.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_parts, b.parts.data(), sizeof(BatchPart) * b.parts.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d_bars, 0, sizeof(Bar) * b.items.size(), s);
+    if (e == hipSuccess)
+        e = launch_batch(d_items, d_parts, (int32_t)b.parts.size(), d_bars, d_arena, flags & SSSP_FLAG_LITERAL,
+                         khz * 10000, ctl, nwg, s);
+    (void)hipFreeAsync(d_items, s);
+    (void)hipFreeAsync(d_parts, s);
+    (void)hipFreeAsync(d_bars, s);
+    if (d_arena) (void)hipFreeAsync(d_arena, s);
+    if (e != hipSuccess) return hip_err(e, "batched launch");
+    return SSSP_OK;
+}
+
+int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
+                           void* stream, sssp_batch_plan** out) {
+    if (!out) return err(SSSP_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_all(inst, count);
+    if (rc) return rc;
+    if (count == 0) return err(SSSP_EINVAL, "empty plan");
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    sssp_batch_plan* p = new sssp_batch_plan();
+    auto fail = [&](int code) {
+        p->free_device();
+        for (auto& c : p->copies) (void)hipFree(c.data);
+        (void)hipFree(p->d_ctl);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->cap) (void)hipStreamDestroy(p->cap);
+        if (p->done) (void)hipEventDestroy(p->done);
+        delete p;
+        return code;
+    };
+    p->flags = flags;
+    (void)hipGetDevice(&p->device);
+    int cus = 0, rate = 0, per_cu = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && rate > 0)
+        p->clock_khz = rate;
+    if (batch_occupancy(&per_cu) != 0 || per_cu < 1) return fail(err(SSSP_EDEVICE, "batched kernel does not fit"));
+    p->nwg = tuning && tuning->workgroups ? std::min(tuning->workgroups, per_cu * cus) : per_cu * cus;
+    p->inst.assign(inst, inst + count);
+    p->src.resize(count);
+    // exact compact copies of the distinct matrices, when asked for and when they fit
+    std::map<std::pair<const int32_t*, int64_t>, int> seen;
+    for (int32_t i = 0; i < count; ++i) {
+        p->src[i] = Source{inst[i].W, inst[i].ld, 4};
+        if (!(flags & SSSP_FLAG_COMPACT)) continue;
+        auto key = std::make_pair(inst[i].W, inst[i].ld);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            CompactCopy c;
+            rc = make_compact(inst[i].W, inst[i].ld, inst[i].n, s, &c);
+            if (rc) return fail(rc);
+            p->copies.push_back(c);
+            it = seen.emplace(key, (int)p->copies.size() - 1).first;
+            if (c.elem < 4) {
+                p->info.compact_graphs += 1;
+                p->info.compact_bytes += (int64_t)c.ld * inst[i].n * c.elem;
+            }
+        }
+        const CompactCopy& c = p->copies[it->second];
+        if (c.elem < 4) p->src[i] = Source{c.data, c.ld, c.elem};
+    }
+    hipError_t e = hipMalloc(&p->d_ctl, ctl_size());
+    if (e == hipSuccess) e = hipMemset(p->d_ctl, 0, ctl_size());
+    if (e != hipSuccess) return fail(err(SSSP_ENOMEM, "plan control block: %s", hipGetErrorString(e)));
+    // workgroups per instance: a single workgroup for n up to the single limit, or gangs
+    // with a given number of columns per member; measured, fastest kept
+    struct Cand {
+        int32_t single_max_n, gang_columns;
+    };
+    std::vector<Cand> cands;
+    int32_t nmax = 0;
+    for (auto& I : p->inst) nmax = std::max(nmax, I.n);
+    if (tuning && tuning->single_max_n > 0) {
+        cands.push_back(Cand{tuning->single_max_n, tuning->gang_columns > 0 ? tuning->gang_columns : 4096});
+    } else {
+        if (nmax <= max_batch_single_n()) cands.push_back(Cand{max_batch_single_n(), 4096});
+        for (int32_t c : {4096, 2048, 1024, 512})
+            if (c < nmax) cands.push_back(Cand{c, c});
+    }
+    double best_ms = 1e30;
+    Cand best = cands.front();
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (cands.size() > 1) {
+        (void)hipEventCreate(&ev0);
+        (void)hipEventCreate(&ev1);
+        for (const Cand& c : cands) {
+            rc = p->upload(c.single_max_n, c.gang_columns);
+            if (rc) continue;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipEventRecord(ev0, s);
+                e = p->enqueue(s);
+                (void)hipEventRecord(ev1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                if (e != hipSuccess) break;
+                float t = 0;
+                (void)hipEventElapsedTime(&t, ev0, ev1);
+                if (rep > 0) ms = std::min(ms, t);  // first run warms caches
+            }
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(ev0);
+                (void)hipEventDestroy(ev1);
+                return fail(hip_err(e, "autotuning launch"));
+            }
+            p->info.candidates += 1;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    rc = p->upload(best.single_max_n, best.gang_columns);
+    if (rc) return fail(rc);
+    p->info.threads = 1024;
+    p->info.workgroups = p->nwg;
+    p->info.single_max_n = best.single_max_n;
+    p->info.gang_columns = best.gang_columns;
+    p->info.tuned_ms = best_ms < 1e29 ? best_ms : -1.0;
+    // capture the launch into a graph, replayed by sssp_batch_plan_launch
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = p->enqueue(p->cap);
+        e = hipStreamEndCapture(p->cap, &p->graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(hip_err(e, "capturing the batched launch"));
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(hip_err(e, "hipEventCreate"));
+    p->info.graph = 1;
+    p->info.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    return SSSP_OK;
+}
+
+int sssp_batch_plan_launch(sssp_batch_plan* p, void* stream) {
+    if (!p) return err(SSSP_EINVAL, "null plan");
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(p->done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_err(e, "hipGraphLaunch");
+    return SSSP_OK;
+}
+
+int sssp_batch_plan_info(const sssp_batch_plan* p, sssp_plan_info* info) {
+    if (!p || !info) return err(SSSP_EINVAL, "null argument");
+    *info = p->info;
+    return SSSP_OK;
+}
+
+int sssp_batch_plan_status(sssp_batch_plan* p, void* stream, int32_t* status, int64_t* stats) {
+    if (!p || !status) return err(SSSP_EINVAL, "null argument");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    Ctl c;
+    if (e == hipSuccess) e = hipMemcpy(&c, p->d_ctl, sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(e, "reading plan status");
+    *status = (int32_t)c.status;
+    if (stats)
+        for (int i = 0; i < kStatCount; ++i) stats[i] = (int64_t)c.last[i];
+    return SSSP_OK;
+}
+
+int sssp_batch_plan_destroy(sssp_batch_plan* p) {
+    if (!p) return SSSP_OK;
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);  // the last launch of the plan has finished
+        (void)hipEventDestroy(p->done);
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    p->free_device();
+    for (auto& c : p->copies) (void)hipFree(c.data);
+    (void)hipFree(p->d_ctl);
+    delete p;
+    return SSSP_OK;
+}
+
+}  // extern "C"

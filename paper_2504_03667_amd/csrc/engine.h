@@ -185,17 +185,79 @@ struct Cols {
     uint32_t vis;  // bit 4k+j: visited, or not a column of the slice/matrix
 };
 
-// Stream rows list[r], list[r + P], ... (m entries in `list`, partition r) of
-// the matrix restricted to the slice into the running per-column minima, U rows
-// in flight per thread.  `width` = columns of the slice that exist in the
-// matrix (<= S).  `vec`: the row segments are 16-byte aligned (W aligned, ld and
-// the slice start multiples of 4), so whole groups are read with one 128-bit
-// load; otherwise, and for a partial last group, entries are read one by one.
+// Matrix entries as stored.  int32_t is the caller's matrix (INT32_MAX = no
+// edge).  uint16_t / uint8_t are exact compact copies that the library builds
+// of a graph it will stream many times, when every finite weight fits below
+// the type's all-ones code, which stands for "no edge".  Four consecutive
+// entries (one column group) are read with one 16-, 8- or 4-byte load and
+// widened to uint32 with the no-edge code mapped back to INT32_MAX.
+template <typename E>
+__device__ __forceinline__ uint32_t widen(uint32_t v);
+template <>
+__device__ __forceinline__ uint32_t widen<int32_t>(uint32_t v) { return v; }
+template <>
+__device__ __forceinline__ uint32_t widen<uint16_t>(uint32_t v) { return v == 0xffffu ? kInf : v; }
+template <>
+__device__ __forceinline__ uint32_t widen<uint8_t>(uint32_t v) { return v == 0xffu ? kInf : v; }
+
+// The matrix always lives in global memory (device or pinned host memory).
+// Descriptors loaded from memory carry generic pointers, which the compiler
+// would access with FLAT instructions; casting to the global address space
+// makes the row loads plain global loads.
+// (The host pass of the same source has no address spaces.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using global_ptr = const __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using global_ptr = const T*;
+#endif
+
+// One column group as loaded (16, 8 or 4 bytes) and its widening to uint32.
+template <typename E>
+struct Raw;
+template <>
+struct Raw<int32_t> {
+    typedef int4 type;
+};
+template <>
+struct Raw<uint16_t> {
+    typedef uint2 type;
+};
+template <>
+struct Raw<uint8_t> {
+    typedef uint32_t type;
+};
+
+template <typename E>
+__device__ __forceinline__ void unpack(const typename Raw<E>::type& x, uint32_t (&w)[4]);
+template <>
+__device__ __forceinline__ void unpack<int32_t>(const int4& x, uint32_t (&w)[4]) {
+    w[0] = (uint32_t)x.x;
+    w[1] = (uint32_t)x.y;
+    w[2] = (uint32_t)x.z;
+    w[3] = (uint32_t)x.w;
+}
+template <>
+__device__ __forceinline__ void unpack<uint16_t>(const uint2& x, uint32_t (&w)[4]) {
+    w[0] = widen<uint16_t>(x.x & 0xffffu);
+    w[1] = widen<uint16_t>(x.x >> 16);
+    w[2] = widen<uint16_t>(x.y & 0xffffu);
+    w[3] = widen<uint16_t>(x.y >> 16);
+}
+template <>
+__device__ __forceinline__ void unpack<uint8_t>(const uint32_t& x, uint32_t (&w)[4]) {
+    w[0] = widen<uint8_t>(x & 0xffu);
+    w[1] = widen<uint8_t>((x >> 8) & 0xffu);
+    w[2] = widen<uint8_t>((x >> 16) & 0xffu);
+    w[3] = widen<uint8_t>(x >> 24);
+}
+
 // Rows list[r], list[r + P], ... of one column group (4 columns starting at p0
-// within each row) into `best`.  FULL: the 4 entries exist and are 16-byte
-// aligned, read with one 128-bit load; otherwise only the first `valid` are read.
-template <int U, bool FULL>
-__device__ __forceinline__ void stream_group(uint64_t (&best)[4], const int32_t* __restrict__ p0, int64_t ld,
+// within each row) into `best`.  FULL: the 4 entries exist and are aligned for
+// one load; otherwise only the first `valid` are read, one by one.
+template <int U, bool FULL, typename E>
+__device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __restrict__ p0, int64_t ld,
                                              int valid, const int32_t* list, int m, int first, int step) {
     for (int i = first; i < m; i += step * U) {
         // past the end of the list, repeat its last row: a duplicate cannot change a minimum
@@ -206,18 +268,21 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const int32_t*
             uu[q] = (uint32_t)list[idx < m ? idx : m - 1];
         }
         uint32_t w[U][4];
+        if (FULL) {
+            // issue all U loads before using any of them: keeps U rows in flight per thread
+            typename Raw<E>::type raw[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int32_t* p = p0 + (int64_t)uu[q] * ld;
-            if (FULL) {
-                const int4 x = *reinterpret_cast<const int4*>(p);
-                w[q][0] = (uint32_t)x.x;
-                w[q][1] = (uint32_t)x.y;
-                w[q][2] = (uint32_t)x.z;
-                w[q][3] = (uint32_t)x.w;
-            } else {
+            for (int q = 0; q < U; ++q)
+                raw[q] = *reinterpret_cast<global_ptr<typename Raw<E>::type>>((global_ptr<E>)p0 + (int64_t)uu[q] * ld);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) w[q][j] = j < valid ? (uint32_t)p[j] : kInf;
+            for (int q = 0; q < U; ++q) unpack<E>(raw[q], w[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const global_ptr<E> p = (global_ptr<E>)p0 + (int64_t)uu[q] * ld;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[q][j] = j < valid ? widen<E>((uint32_t)p[j]) : kInf;
             }
         }
 #pragma unroll
@@ -227,8 +292,14 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const int32_t*
     }
 }
 
-template <int G, int U>
-__device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const int32_t* __restrict__ W,
+// Stream rows list[r], list[r + P], ... (m entries in `list`, partition r) of
+// the matrix restricted to the slice into the running per-column minima, U rows
+// in flight per thread.  `width` = columns of the slice that exist in the
+// matrix (<= S).  `vec`: row segments are aligned for whole-group loads (W
+// aligned, ld and the slice start multiples of 4); otherwise, and for a
+// partial last group, entries are read one by one.
+template <int G, int U, typename E>
+__device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const E* __restrict__ W,
                                             int64_t ld, int64_t col0, int width, bool vec,
                                             const int32_t* list, int m) {
     // One column group at a time keeps only U x 4 weights live per thread.
@@ -236,11 +307,11 @@ __device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const
     for (int k = 0; k < G; ++k) {
         const int v0 = 4 * (lo.c + k * lo.L);
         if (v0 >= width) continue;
-        const int32_t* p0 = W + col0 + v0;
+        const E* p0 = W + col0 + v0;
         if (vec && v0 + 3 < width)
-            stream_group<U, true>(cs.best[k], p0, ld, 4, list, m, lo.r, lo.P);
+            stream_group<U, true, E>(cs.best[k], p0, ld, 4, list, m, lo.r, lo.P);
         else
-            stream_group<U, false>(cs.best[k], p0, ld, min(4, width - v0), list, m, lo.r, lo.P);
+            stream_group<U, false, E>(cs.best[k], p0, ld, min(4, width - v0), list, m, lo.r, lo.P);
     }
 }
 

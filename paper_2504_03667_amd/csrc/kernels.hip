@@ -46,6 +46,11 @@ struct SolveStats {
     uint32_t status;
 };
 
+// The workgroup's LDS state, at namespace scope so that solver variants compiled
+// as separate functions still address it as LDS.
+template <int T>
+__shared__ SharedSolve<T> g_sh;
+
 // bit of local column v (0 <= v < width) if this thread owns it, else 0
 __device__ __forceinline__ uint32_t owner_bit(const Layout& lo, int64_t v, int width) {
     if (v < 0 || v >= width || lo.r != 0) return 0;
@@ -58,8 +63,8 @@ __device__ __forceinline__ uint32_t owner_bit(const Layout& lo, int64_t v, int w
 // ---------------------------------------------------------------------------
 // One workgroup, whole row.
 // ---------------------------------------------------------------------------
-template <int T, int G, int U>
-__device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
+template <int T, int G, int U, typename E>
+__device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                              int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec,
                              bool literal, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
     const Layout lo = make_layout<T>(n);
@@ -81,7 +86,7 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
             M = 1;
             if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
             __syncthreads();
-            stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
+            stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
             const uint32_t base = block_excl_scan<T>(__popc(bucket), M, sh.red);
@@ -97,7 +102,7 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
                             ++rank;
                         }
                 __syncthreads();
-                stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
+                stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
                 __syncthreads();
             }
         }
@@ -118,7 +123,7 @@ __device__ void solve_single(const int32_t* __restrict__ W, int64_t ld, int32_t 
                 reset_best(cs);
                 if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
                 __syncthreads();
-                stream_rows<G, U>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
+                stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
                 merge_partitions<T, G>(cs, lo, sh.mrg);
                 bucket = owner_bit(lo, u0, n);
                 M = 1;
@@ -142,10 +147,10 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
                                               int32_t src, int32_t* __restrict__ dist,
                                               int32_t* __restrict__ pred, uint32_t flags,
                                               Ctl* __restrict__ ctl) {
-    __shared__ SharedSolve<T> sh;
+    SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
     const bool vec = (flags & kFlagVec) != 0;
-    solve_single<T, G, U>(W, ld, n, src, dist, pred, vec, (flags & kFlagLiteral) != 0, sh, st, ctl);
+    solve_single<T, G, U, int32_t>(W, ld, n, src, dist, pred, vec, (flags & kFlagLiteral) != 0, sh, st, ctl);
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
     block_min_or<T>(dummy, s, sh.red);
@@ -301,8 +306,8 @@ __device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const 
 // Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
 // entries (double-buffered by barrier parity).  Returns false if a barrier
 // wait timed out.  `trace` (may be null) receives rank 0's round trace.
-template <int T, int G, int U>
-__device__ bool solve_gang(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
+template <int T, int G, int U, typename E>
+__device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                            int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
                            int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
                            int32_t* __restrict__ lists, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
@@ -344,7 +349,7 @@ __device__ bool solve_gang(const int32_t* __restrict__ W, int64_t ld, int32_t n,
                 reset_best(cs);
                 if (threadIdx.x == 0) sh.list[0] = (int32_t)pu0;
                 __syncthreads();
-                stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+                stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
                 merge_partitions<T, G>(cs, lo, sh.mrg);
                 if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, owner_bit(lo, (int64_t)pu0 - col0, width), pred);
                 else reset_best(cs);
@@ -378,7 +383,7 @@ __device__ bool solve_gang(const int32_t* __restrict__ W, int64_t ld, int32_t n,
             bucket = owner_bit(lo, (int64_t)u0 - col0, width);
             if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
             __syncthreads();
-            stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+            stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
             const uint32_t c = ((int)threadIdx.x < nwg && (uint32_t)(rec.key >> 32) == d) ? rec.count : 0u;
@@ -395,7 +400,7 @@ __device__ bool solve_gang(const int32_t* __restrict__ W, int64_t ld, int32_t n,
                 sh.list[threadIdx.x] = nxt;
                 __syncthreads();
                 if (e0 + kCap < M) nxt = gather_entry<T>(sh, rl, nwg, S, e0 + kCap, M);
-                stream_rows<G, U>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
+                stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
                 __syncthreads();
             }
         }
@@ -443,46 +448,145 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                                             int32_t* __restrict__ pred, uint32_t flags, int32_t S,
                                             long long timeout, Ctl* __restrict__ ctl,
                                             Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
-    __shared__ SharedSolve<T> sh;
+    SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
-    solve_gang<T, G, U>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
+    solve_gang<T, G, U, int32_t>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
                         blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl);
     finish_launch(ctl, st, blockIdx.x == 0);
 }
 
 // ---------------------------------------------------------------------------
-// Batched: independent workgroups pull instances from a ticket counter.
+// One item (a batched instance or a served query) solved by the workgroup that
+// claimed it alone, or by rank `part` of a gang of item.parts workgroups.
+// ---------------------------------------------------------------------------
+// Each (matrix type, columns-per-thread) variant is compiled as a function of
+// its own, so that its register allocation does not pay for the others.
+template <int T, int G, typename E>
+__device__ __attribute__((noinline)) SolveStats single_variant(BatchItem I, bool literal) {
+    SolveStats st = {0, 0, 0, 0, 0};
+    solve_single<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, literal,
+                             g_sh<T>, st, nullptr);
+    uint32_t s = st.status;
+    uint64_t dummy = kNoKey;
+    block_min_or<T>(dummy, s, g_sh<T>.red);
+    st.status = s;
+    return st;
+}
+
+template <int T, int G, typename E>
+__device__ __attribute__((noinline)) SolveStats gang_variant(BatchItem I, int part, bool literal, long long timeout,
+                                                             Bar* bw, char* arena) {
+    SolveStats st = {0, 0, 0, 0, 0};
+    Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
+    int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * I.parts);
+    solve_gang<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, literal, I.S,
+                           part, I.parts, timeout, bw, pubs, lists, g_sh<T>, st, nullptr);
+    if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
+    return st;
+}
+
+template <int T, typename E>
+__device__ __forceinline__ SolveStats single_by_size(const BatchItem& I, bool literal) {
+    const int groups = (I.n + 3) / 4;
+    if (groups <= T) return single_variant<T, 1, E>(I, literal);
+    if (groups <= 2 * T) return single_variant<T, 2, E>(I, literal);
+    return single_variant<T, 4, E>(I, literal);
+}
+
+template <int T, typename E>
+__device__ __forceinline__ SolveStats gang_by_size(const BatchItem& I, int part, bool literal, long long timeout,
+                                                   Bar* bw, char* arena) {
+    const int groups = (I.S + 3) / 4;
+    if (groups <= T) return gang_variant<T, 1, E>(I, part, literal, timeout, bw, arena);
+    if (groups <= 2 * T) return gang_variant<T, 2, E>(I, part, literal, timeout, bw, arena);
+    return gang_variant<T, 4, E>(I, part, literal, timeout, bw, arena);
+}
+
+template <int T>
+__device__ __forceinline__ SolveStats solve_item(const BatchItem& I, int part, bool literal, long long timeout,
+                                                 Bar* bw, char* arena) {
+    if (I.parts <= 1) {
+        if (I.elem == 1) return single_by_size<T, uint8_t>(I, literal);
+        if (I.elem == 2) return single_by_size<T, uint16_t>(I, literal);
+        return single_by_size<T, int32_t>(I, literal);
+    }
+    if (I.elem == 1) return gang_by_size<T, uint8_t>(I, part, literal, timeout, bw, arena);
+    if (I.elem == 2) return gang_by_size<T, uint16_t>(I, part, literal, timeout, bw, arena);
+    return gang_by_size<T, int32_t>(I, part, literal, timeout, bw, arena);
+}
+
+// ---------------------------------------------------------------------------
+// Batched: a grid of workgroups pulls tickets from a counter; each ticket is one
+// part of one item (items are ordered largest first, an item's parts are
+// consecutive tickets, so at most the newest gang is incomplete at a time).
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(T) void k_batch(const sssp_instance* __restrict__ inst, int32_t count,
-                                             const int32_t* __restrict__ order, uint32_t flags,
-                                             Ctl* __restrict__ ctl) {
-    __shared__ SharedSolve<T> sh;
-    SolveStats st = {0, 0, 0, 0, 0};
+__global__ __launch_bounds__(T) void k_batch(const BatchItem* __restrict__ items, const BatchPart* __restrict__ parts,
+                                             int32_t nparts, Bar* __restrict__ bars, char* __restrict__ arena,
+                                             uint32_t flags, long long timeout, Ctl* __restrict__ ctl) {
+    SharedSolve<T>& sh = g_sh<T>;
+    SolveStats total = {0, 0, 0, 0, 0};
     const bool literal = (flags & kFlagLiteral) != 0;
     for (;;) {
         if (threadIdx.x == 0)
             sh.item = (int32_t)__hip_atomic_fetch_add(&ctl->next_item, 1ull, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int32_t i = sh.item;
+        const int32_t t = sh.item;
         __syncthreads();
-        if (i >= count) break;
-        const sssp_instance I = inst[order ? order[i] : i];
-        const bool vec = ((uintptr_t)I.W % 16 == 0) && (I.ld % 4 == 0);
-        const int groups = (I.n + 3) / 4;
-        if (groups <= T)
-            solve_single<T, 1, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
-        else if (groups <= 2 * T)
-            solve_single<T, 2, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
-        else
-            solve_single<T, 4, 8>(I.W, I.ld, I.n, I.src, I.dist, I.pred, vec, literal, sh, st, nullptr);
+        if (t >= nparts) break;
+        const BatchPart pt = parts[t];
+        const BatchItem I = items[pt.item];
+        const SolveStats st = solve_item<T>(I, pt.part, literal, timeout, bars ? &bars[pt.item] : nullptr, arena);
+        total.status |= st.status;
+        if (pt.part == 0) {  // every gang member computes the same counts; count them once
+            total.rounds += st.rounds;
+            total.settled += st.settled;
+            total.fallbacks += st.fallbacks;
+            total.barriers += st.barriers;
+        }
     }
-    uint32_t s = st.status;
-    uint64_t dummy = kNoKey;
-    block_min_or<T>(dummy, s, sh.red);
-    st.status = s;
-    finish_launch(ctl, st, true);
+    finish_launch(ctl, total, true);
+}
+
+// Weight range of a matrix: out[0] = min over all entries, out[1] = max over
+// entries other than INT32_MAX (no edge).  out must hold {INT32_MAX, INT32_MIN}.
+__global__ void k_weight_range(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t* __restrict__ out) {
+    __shared__ int32_t smin[256], smax[256];
+    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / n, j = e - i * n;
+        const int32_t w = W[i * ld + j];
+        mn = min(mn, w);
+        if (w != 0x7fffffff) mx = max(mx, w);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(&out[0], smin[0]);
+        atomicMax(&out[1], smax[0]);
+    }
+}
+
+// Exact compact copy: INT32_MAX -> the all-ones code of E, other entries as is
+// (the caller has checked that they fit below it).  Row stride ldc entries.
+template <typename E>
+__global__ void k_compact(const int32_t* __restrict__ W, int64_t ld, int32_t n, E* __restrict__ C, int64_t ldc) {
+    const E none = (E)~(E)0;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y)
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ldc; j += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t w = j < n ? W[i * ld + j] : 0x7fffffff;
+            C[i * ldc + j] = w == 0x7fffffff ? none : (E)w;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -543,43 +647,14 @@ __device__ __forceinline__ bool serve_claim(const ServeArgs& a, ServeDesc* out) 
 
 template <int T>
 __global__ __launch_bounds__(T) void k_serve(ServeArgs a) {
-    __shared__ SharedSolve<T> sh;
+    SharedSolve<T>& sh = g_sh<T>;
     __shared__ ServeDesc q;
     __shared__ int32_t leave;
     for (;;) {
         if (threadIdx.x == 0) leave = serve_claim(a, &q) ? 1 : 0;
         __syncthreads();
         if (leave) break;
-        SolveStats st = {0, 0, 0, 0, 0};
-        const bool vec = ((uintptr_t)q.W % 16 == 0) && (q.ld % 4 == 0);
-        if (q.parts <= 1) {
-            const int groups = (q.n + 3) / 4;
-            if (groups <= T)
-                solve_single<T, 1, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
-            else if (groups <= 2 * T)
-                solve_single<T, 2, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
-            else
-                solve_single<T, 4, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, sh, st, nullptr);
-            uint32_t s = st.status;
-            uint64_t dummy = kNoKey;
-            block_min_or<T>(dummy, s, sh.red);
-            st.status = s;
-        } else {
-            Pub* pubs = reinterpret_cast<Pub*>(a.arena + q.scratch_off);
-            int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * q.parts);
-            Bar* bw = &a.bars[q.qslot];
-            const int groups = (q.S + 3) / 4;
-            if (groups <= T)
-                solve_gang<T, 1, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
-                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
-            else if (groups <= 2 * T)
-                solve_gang<T, 2, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
-                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
-            else
-                solve_gang<T, 4, 8>(q.W, q.ld, q.n, q.src, q.dist, q.pred, vec, false, q.S, q.part, q.parts,
-                                    a.timeout, bw, pubs, lists, sh, st, nullptr);
-            if (threadIdx.x == 0) gang_leave(bw, (uint32_t)q.parts);
-        }
+        const SolveStats st = solve_item<T>(q.item, q.part, false, a.timeout, &a.bars[q.qslot], a.arena);
         // completion: the last part to finish writes the slot's record to host memory
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -588,7 +663,7 @@ __global__ __launch_bounds__(T) void k_serve(ServeArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (st.status) __hip_atomic_fetch_or(&sl->status, st.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t prev = __hip_atomic_fetch_add(&sl->done_parts, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == (uint32_t)q.parts - 1) {
+            if (prev == (uint32_t)q.item.parts - 1) {
                 const uint32_t status = __hip_atomic_exchange(&sl->status, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&sl->done_parts, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ServeDone* dn = &a.done[q.qslot];
@@ -668,22 +743,36 @@ int grid_occupancy(int slice, int* per_cu) {
     return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 1024, 0);
 }
 
-hipError_t launch_batch(const sssp_instance* d_inst, int32_t count, const int32_t* d_order,
-                        uint32_t flags, Ctl* ctl, int threads, int nwg, hipStream_t s) {
-    if (threads <= 256)
-        hipLaunchKernelGGL((k_batch<256>), dim3(nwg), dim3(256), 0, s, d_inst, count, d_order, flags, ctl);
-    else
-        hipLaunchKernelGGL((k_batch<1024>), dim3(nwg), dim3(1024), 0, s, d_inst, count, d_order, flags, ctl);
+hipError_t launch_batch(const BatchItem* items, const BatchPart* parts, int32_t nparts, Bar* bars, char* arena,
+                        uint32_t flags, long long timeout, Ctl* ctl, int nwg, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<1024>), dim3(nwg), dim3(1024), 0, s, items, parts, nparts, bars, arena, flags,
+                       timeout, ctl);
     return hipGetLastError();
 }
 
-int batch_occupancy(int threads, int* per_cu) {
-    const void* f = threads <= 256 ? reinterpret_cast<const void*>(&k_batch<256>)
-                                   : reinterpret_cast<const void*>(&k_batch<1024>);
-    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, threads <= 256 ? 256 : 1024, 0);
+int batch_occupancy(int* per_cu) {
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(&k_batch<1024>),
+                                                             1024, 0);
 }
 
-int max_batch_n(int threads) { return 4 * 4 * (threads <= 256 ? 256 : 1024); }
+int max_batch_single_n() { return 4 * 4 * 1024; }
+int max_batch_slice() { return 4 * 4 * 1024; }
+
+hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_range, dim3(2048), dim3(256), 0, s, W, ld, n, d_out2);
+    return hipGetLastError();
+}
+
+hipError_t compact_copy(const int32_t* W, int64_t ld, int32_t n, void* C, int64_t ldc, int elem, hipStream_t s) {
+    dim3 grid((unsigned)((ldc + 255) / 256 < 64 ? (ldc + 255) / 256 : 64), (unsigned)(n < 65535 ? n : 65535));
+    if (elem == 1)
+        hipLaunchKernelGGL((k_compact<uint8_t>), grid, dim3(256), 0, s, W, ld, n, static_cast<uint8_t*>(C), ldc);
+    else if (elem == 2)
+        hipLaunchKernelGGL((k_compact<uint16_t>), grid, dim3(256), 0, s, W, ld, n, static_cast<uint16_t*>(C), ldc);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_serve(const ServeArgs& a, int nwg, hipStream_t s) {
     hipLaunchKernelGGL((k_serve<1024>), dim3(nwg), dim3(1024), 0, s, a);

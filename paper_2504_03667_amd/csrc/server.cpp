@@ -53,9 +53,13 @@ int err(int code, const char* fmt, ...) {
 }
 
 struct Graph {
-    const int32_t* W;
+    const int32_t* W;  // the caller's matrix
     int64_t ld;
     int32_t n;
+    const void* Ws;    // what is streamed: W, or the server's compact copy
+    int64_t lds;
+    int32_t elem;
+    void* owned;       // compact copy to free on destroy
 };
 
 enum { kPending = 0, kRunning = 1, kDone = 2 };
@@ -207,18 +211,21 @@ struct sssp_server {
             for (int32_t j = 0; j < q.parts; ++j) {
                 ServeDesc d;
                 memset(&d, 0, sizeof d);
-                d.W = g.W;
-                d.ld = g.ld;
-                d.dist = q.dist;
-                d.pred = q.pred;
-                d.n = g.n;
-                d.src = q.src;
+                BatchItem& it = d.item;
+                it.W = g.Ws;
+                it.ld = g.lds;
+                it.elem = g.elem;
+                it.vec = ((uintptr_t)g.Ws % (4 * (uintptr_t)g.elem)) == 0 && g.lds % 4 == 0;
+                it.dist = q.dist;
+                it.pred = q.pred;
+                it.n = g.n;
+                it.src = q.src;
+                it.parts = q.parts;
+                it.S = q.S;
+                it.scratch_off = off;
                 d.part = j;
-                d.parts = q.parts;
-                d.S = q.S;
                 d.qslot = (uint32_t)qs;
                 d.ticket = pending.front();
-                d.scratch_off = off;
                 ring[(tail + j) % (uint64_t)cfg.ring_slots] = d;
             }
             tail += (uint64_t)q.parts;
@@ -336,6 +343,8 @@ int host_alloc(X** p, size_t count, const char* what) {
 }
 
 void release_all(sssp_server* s) {
+    for (auto& g : s->graphs)
+        if (g.owned) (void)hipFree(g.owned);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     (void)hipHostFree(s->ctl);
     (void)hipHostFree(s->ring);
@@ -401,15 +410,43 @@ int sssp_server_create(const sssp_server_config* cfg_in, sssp_server** out) {
     return SSSP_OK;
 }
 
-int sssp_server_add_graph(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, int32_t* graph_id) {
+int sssp_server_add_graph_ex(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, uint32_t flags,
+                             int32_t* graph_id) {
     if (!s || !W || !graph_id) return err(SSSP_EINVAL, "null argument");
     if (n < 1 || ld < n) return err(SSSP_EINVAL, "need n >= 1 and ld >= n (n=%d ld=%lld)", n, (long long)ld);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        int32_t parts, S;
+        s->plan(n, &parts, &S);
+        if (S > max_serve_slice()) return err(SSSP_EUNSUPPORTED, "n=%d is too large for this server", n);
+    }
+    Graph g{W, ld, n, W, ld, 4, nullptr};
+    if (flags & SSSP_FLAG_COMPACT) {
+        // built on a stream of its own: the server's stream holds the resident kernel
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return err(SSSP_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        CompactCopy c;
+        const int rc = make_compact(W, ld, n, cs, &c);
+        (void)hipStreamDestroy(cs);
+        if (rc) return rc;
+        if (c.elem < 4) g = Graph{W, ld, n, c.data, c.ld, c.elem, c.data};
+    }
     std::lock_guard<std::mutex> lk(s->mu);
-    int32_t parts, S;
-    s->plan(n, &parts, &S);
-    if (S > max_serve_slice()) return err(SSSP_EUNSUPPORTED, "n=%d is too large for this server", n);
-    s->graphs.push_back(Graph{W, ld, n});
+    s->graphs.push_back(g);
     *graph_id = (int32_t)s->graphs.size() - 1;
+    return SSSP_OK;
+}
+
+int sssp_server_add_graph(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, int32_t* graph_id) {
+    return sssp_server_add_graph_ex(s, W, ld, n, 0u, graph_id);
+}
+
+int sssp_server_graph_elem(sssp_server* s, int32_t graph_id, int32_t* elem_bytes) {
+    if (!s || !elem_bytes) return err(SSSP_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) return err(SSSP_ENOGRAPH, "unknown graph %d", graph_id);
+    *elem_bytes = s->graphs[graph_id].elem;
     return SSSP_OK;
 }
 

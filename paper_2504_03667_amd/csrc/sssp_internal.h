@@ -37,10 +37,46 @@ hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pu
 int max_grid_slice();
 int grid_occupancy(int slice, int* per_cu);
 
-hipError_t launch_batch(const sssp_instance* d_inst, int32_t count, const int32_t* d_order,
-                        uint32_t flags, Ctl* ctl, int threads, int nwg, hipStream_t s);
-int batch_occupancy(int threads, int* per_cu);
-int max_batch_n(int threads);
+// One instance of a batched launch or one served query, as the kernels read it.
+struct BatchItem {
+    const void* W;       // int32_t, uint16_t or uint8_t entries (elem bytes each)
+    int64_t ld;          // row stride in entries
+    int32_t* dist;
+    int32_t* pred;
+    int32_t n;
+    int32_t src;
+    int32_t elem;        // 4: the caller's int32 matrix; 2 / 1: an exact compact copy
+    int32_t vec;         // rows aligned for whole-group loads
+    int32_t parts;       // workgroups that solve it (1: one workgroup alone; > 1: a gang)
+    int32_t S;           // columns per gang member
+    unsigned long long scratch_off;  // byte offset of a gang's records and lists in the arena
+};
+
+// Ticket t of a batched launch is part parts[t].part of item parts[t].item;
+// the parts of one item are consecutive.
+struct BatchPart {
+    int32_t item;
+    int32_t part;
+};
+
+hipError_t launch_batch(const BatchItem* items, const BatchPart* parts, int32_t nparts, Bar* bars, char* arena,
+                        uint32_t flags, long long timeout, Ctl* ctl, int nwg, hipStream_t s);
+int batch_occupancy(int* per_cu);
+int max_batch_single_n();
+int max_batch_slice();
+
+// Exact compact copy of a matrix (see make_compact).
+struct CompactCopy {
+    void* data = nullptr;  // null when the weights do not fit a narrower type
+    int64_t ld = 0;        // row stride in entries
+    int elem = 4;          // 1, 2, or 4 (no copy)
+    int32_t wmin = 0, wmax = 0;
+};
+int make_compact(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, CompactCopy* out);
+
+// Exact compact copies (int32 -> uint16 / uint8) and weight ranges.
+hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out2, hipStream_t s);
+hipError_t compact_copy(const int32_t* W, int64_t ld, int32_t n, void* C, int64_t ldc, int elem, hipStream_t s);
 
 size_t ctl_size();
 size_t pub_size();
@@ -67,18 +103,10 @@ struct ServeControl {
 // the query is solved by one workgroup alone).  Written by the host into the
 // ring (pinned host memory) before `tail` is advanced past it.
 struct ServeDesc {
-    const int32_t* W;
-    int64_t ld;
-    int32_t* dist;
-    int32_t* pred;
-    int32_t n;
-    int32_t src;
+    BatchItem item;
     int32_t part;
-    int32_t parts;
-    int32_t S;               // columns per gang member
-    uint32_t qslot;          // in-flight query slot (device state, completion record)
+    uint32_t qslot;  // in-flight query slot (device state, completion record)
     unsigned long long ticket;
-    unsigned long long scratch_off;  // byte offset of the gang's records and lists in the arena
 };
 
 // Completion record of a query slot, written by the GPU into pinned host memory.

@@ -29,6 +29,7 @@ SSSP_STATUS_ZERO_FALLBACK = 4
 SSSP_FLAG_LITERAL = 1
 SSSP_FLAG_SINGLE = 2
 SSSP_FLAG_GRID = 4
+SSSP_FLAG_COMPACT = 8
 
 SSSP_STAT_ROUNDS, SSSP_STAT_SETTLED, SSSP_STAT_FALLBACKS, SSSP_STAT_BARRIERS = range(4)
 
@@ -43,7 +44,17 @@ class SsspError(RuntimeError):
 
 class sssp_tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("single_max_n", ctypes.c_int32), ("gang_columns", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class sssp_plan_info(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("single_max_n", ctypes.c_int32), ("gang_columns", ctypes.c_int32),
+                ("max_parts", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("compact_graphs", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("compact_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_double),
+                ("build_ms", ctypes.c_double)]
 
 
 class sssp_instance(ctypes.Structure):
@@ -99,6 +110,15 @@ def lib():
                                       ctypes.POINTER(I32)]
         L.sssp_last_trace.restype = ctypes.c_int
         L.sssp_batch_max_n.restype = I32
+        L.sssp_batch_plan_create.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
+                                             ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(P)]
+        L.sssp_batch_plan_launch.argtypes = [P, P]
+        L.sssp_batch_plan_info.argtypes = [P, ctypes.POINTER(sssp_plan_info)]
+        L.sssp_batch_plan_status.argtypes = [P, P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+        L.sssp_batch_plan_destroy.argtypes = [P]
+        L.sssp_dense_validate.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+        L.sssp_server_add_graph_ex.argtypes = [P, P, I64, I32, U32, ctypes.POINTER(I32)]
+        L.sssp_server_graph_elem.argtypes = [P, I32, ctypes.POINTER(I32)]
         L.sssp_single_max_n.restype = I32
         L.sssp_server_now_ns.restype = I64
         L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
@@ -136,11 +156,12 @@ def _ptr(t, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _tuning(threads=0, workgroups=0):
-    if not threads and not workgroups:
+def _tuning(threads=0, workgroups=0, single_max_n=0, gang_columns=0):
+    if not (threads or workgroups or single_max_n or gang_columns):
         return None
     t = sssp_tuning()
     t.threads, t.workgroups = threads, workgroups
+    t.single_max_n, t.gang_columns = single_max_n, gang_columns
     return ctypes.byref(t)
 
 
@@ -203,6 +224,77 @@ def sssp_dense_solve_batched(items, flags=0, threads=0, workgroups=0, stream=Non
                                                  _stream(stream)))
 
 
+def sssp_batch_max_n():
+    return lib().sssp_batch_max_n()
+
+
+def sssp_dense_validate(W, ld, n, stream=None):
+    """(min weight, max finite weight) of an int32 device matrix; synchronous."""
+    mn, mx = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().sssp_dense_validate(_ptr(W, "W"), ld, n, ctypes.byref(mn), ctypes.byref(mx), _stream(stream)))
+    return mn.value, mx.value
+
+
+def sssp_batch_plan_create(items, flags=0, threads=0, workgroups=0, single_max_n=0, gang_columns=0,
+                           stream=None):
+    arr, count = make_instances(items)
+    h = ctypes.c_void_p()
+    _check(lib().sssp_batch_plan_create(arr, count, flags, _tuning(threads, workgroups, single_max_n,
+                                                                    gang_columns),
+                                        _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def sssp_batch_plan_launch(h, stream=None):
+    return _check(lib().sssp_batch_plan_launch(h, _stream(stream)))
+
+
+def sssp_batch_plan_info(h):
+    i = sssp_plan_info()
+    _check(lib().sssp_batch_plan_info(h, ctypes.byref(i)))
+    return {k: getattr(i, k) for k, _ in sssp_plan_info._fields_}
+
+
+def sssp_batch_plan_status(h, stream=None):
+    st = ctypes.c_int32(0)
+    stats = (ctypes.c_int64 * 4)()
+    _check(lib().sssp_batch_plan_status(h, _stream(stream), ctypes.byref(st), stats))
+    return st.value, list(stats)
+
+
+def sssp_batch_plan_destroy(h):
+    return _check(lib().sssp_batch_plan_destroy(h))
+
+
+class BatchPlan:
+    """Owns an sssp_batch_plan and keeps the tensors of its instances alive."""
+
+    def __init__(self, items, flags=0, **tuning):
+        self.items = list(items)
+        self.h = sssp_batch_plan_create(self.items, flags, **tuning)
+
+    def launch(self, stream=None):
+        sssp_batch_plan_launch(self.h, stream)
+
+    def info(self):
+        return sssp_batch_plan_info(self.h)
+
+    def status(self, stream=None):
+        return sssp_batch_plan_status(self.h, stream)
+
+    def close(self):
+        if self.h is not None:
+            sssp_batch_plan_destroy(self.h)
+            self.h = None
+            self.items = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 # ---- convenience wrappers (allocate outputs, return tensors) ----
 
 def solve(W, src, flags=0, threads=0, workgroups=0, stream=None):
@@ -233,6 +325,18 @@ def sssp_server_add_graph(h, W, ld, n):
     gid = ctypes.c_int32(-1)
     _check(lib().sssp_server_add_graph(h, _ptr(W, "W"), ld, n, ctypes.byref(gid)))
     return gid.value
+
+
+def sssp_server_add_graph_ex(h, W, ld, n, flags=0):
+    gid = ctypes.c_int32(-1)
+    _check(lib().sssp_server_add_graph_ex(h, _ptr(W, "W"), ld, n, flags, ctypes.byref(gid)))
+    return gid.value
+
+
+def sssp_server_graph_elem(h, graph_id):
+    e = ctypes.c_int32(0)
+    _check(lib().sssp_server_graph_elem(h, graph_id, ctypes.byref(e)))
+    return e.value
 
 
 def sssp_server_submit(h, graph_id, src, dist, pred):
@@ -278,10 +382,13 @@ class Server:
         self._graphs = []
         self._outs = {}
 
-    def add_graph(self, W):
-        gid = sssp_server_add_graph(self.h, W, W.stride(0), W.shape[0])
+    def add_graph(self, W, flags=0):
+        gid = sssp_server_add_graph_ex(self.h, W, W.stride(0), W.shape[0], flags)
         self._graphs.append(W)
         return gid
+
+    def graph_elem(self, graph_id):
+        return sssp_server_graph_elem(self.h, graph_id)
 
     def submit(self, graph_id, src, dist, pred):
         t = sssp_server_submit(self.h, graph_id, src, dist, pred)

@@ -162,3 +162,22 @@ def test_server_workload_sample(sp):
             code, where = oracle.certificate(W, q.src, dd, pp)
             assert code == 0, (q, oracle.CERT_CODES[code], where)
             assert np.array_equal(oracle.closed_form_pred(W, dd), pp)
+
+
+def test_server_compact_graphs(sp):
+    """Graphs registered with SSSP_FLAG_COMPACT are streamed from exact 8/16-bit copies and
+    give the same results as the int32 matrices."""
+    rng = np.random.default_rng(204)
+    graphs = [random_dense(rng, 1200, 0.05, 1, 100), random_dense(rng, 5000, 0.01, 1, 1000),
+              random_dense(rng, 900, 0.1, 1, 70000)]
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    plan = [(g, int(rng.integers(0, graphs[g].shape[0])), *outputs(graphs[g].shape[0]))
+            for g in (0, 1, 2, 1, 0, 2, 1)]
+    with sp.Server() as srv:
+        gids = [srv.add_graph(W, sp.SSSP_FLAG_COMPACT) for W in dev]
+        assert [srv.graph_elem(g) for g in gids] == [1, 2, 4]
+        jobs = [(g, src, d, p, srv.submit(gids[g], src, d, p)) for g, src, d, p in plan]
+        for g, src, d, p, t in jobs:
+            srv.wait(t, timeout_s=60)
+            dr, pr, _ = oracle.dijkstra(graphs[g], src)
+            assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr)
