@@ -181,8 +181,9 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         if (e != hipSuccess) return hip_fail(e, "launch(one-workgroup solve)");
     } else {
         int per_cu = 0;
-        // slice width: about 256 columns (1 KiB of each row) per workgroup by default
-        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 255) / 256);
+        // slice width: about 128 columns (512 B of each row) per workgroup by default, as
+        // many workgroups as fit; wider slices when n outgrows the grid
+        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 127) / 128);
         int S = (int)(((int64_t)n + want - 1) / want);
         S = (S + 3) & ~3;
         if (S > max_grid_slice()) S = max_grid_slice();

@@ -216,13 +216,15 @@ using global_ptr = const T*;
 // One column group as loaded (16, 8 or 4 bytes) and its widening to uint32.
 template <typename E>
 struct Raw;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
 template <>
 struct Raw<int32_t> {
-    typedef int4 type;
+    typedef v4i type;
 };
 template <>
 struct Raw<uint16_t> {
-    typedef uint2 type;
+    typedef v2u type;
 };
 template <>
 struct Raw<uint8_t> {
@@ -232,14 +234,14 @@ struct Raw<uint8_t> {
 template <typename E>
 __device__ __forceinline__ void unpack(const typename Raw<E>::type& x, uint32_t (&w)[4]);
 template <>
-__device__ __forceinline__ void unpack<int32_t>(const int4& x, uint32_t (&w)[4]) {
+__device__ __forceinline__ void unpack<int32_t>(const v4i& x, uint32_t (&w)[4]) {
     w[0] = (uint32_t)x.x;
     w[1] = (uint32_t)x.y;
     w[2] = (uint32_t)x.z;
     w[3] = (uint32_t)x.w;
 }
 template <>
-__device__ __forceinline__ void unpack<uint16_t>(const uint2& x, uint32_t (&w)[4]) {
+__device__ __forceinline__ void unpack<uint16_t>(const v2u& x, uint32_t (&w)[4]) {
     w[0] = widen<uint16_t>(x.x & 0xffffu);
     w[1] = widen<uint16_t>(x.x >> 16);
     w[2] = widen<uint16_t>(x.y & 0xffffu);
@@ -255,8 +257,10 @@ __device__ __forceinline__ void unpack<uint8_t>(const uint32_t& x, uint32_t (&w)
 
 // Rows list[r], list[r + P], ... of one column group (4 columns starting at p0
 // within each row) into `best`.  FULL: the 4 entries exist and are aligned for
-// one load; otherwise only the first `valid` are read, one by one.
-template <int U, bool FULL, typename E>
+// one load; otherwise only the first `valid` are read, one by one.  NT: the
+// loads carry the nontemporal hint, for matrices streamed once per solve (the
+// whole-GPU solve) rather than reused from the caches across instances.
+template <int U, bool FULL, typename E, bool NT>
 __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __restrict__ p0, int64_t ld,
                                              int valid, const int32_t* list, int m, int first, int step) {
     for (int i = first; i < m; i += step * U) {
@@ -272,8 +276,11 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __res
             // issue all U loads before using any of them: keeps U rows in flight per thread
             typename Raw<E>::type raw[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q)
-                raw[q] = *reinterpret_cast<global_ptr<typename Raw<E>::type>>((global_ptr<E>)p0 + (int64_t)uu[q] * ld);
+            for (int q = 0; q < U; ++q) {
+                const global_ptr<typename Raw<E>::type> a =
+                    reinterpret_cast<global_ptr<typename Raw<E>::type>>((global_ptr<E>)p0 + (int64_t)uu[q] * ld);
+                raw[q] = NT ? __builtin_nontemporal_load(a) : *a;
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < U; ++q) unpack<E>(raw[q], w[q]);
@@ -298,7 +305,7 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __res
 // matrix (<= S).  `vec`: row segments are aligned for whole-group loads (W
 // aligned, ld and the slice start multiples of 4); otherwise, and for a
 // partial last group, entries are read one by one.
-template <int G, int U, typename E>
+template <int G, int U, typename E, bool NT = false>
 __device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const E* __restrict__ W,
                                             int64_t ld, int64_t col0, int width, bool vec,
                                             const int32_t* list, int m) {
@@ -309,9 +316,9 @@ __device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const
         if (v0 >= width) continue;
         const E* p0 = W + col0 + v0;
         if (vec && v0 + 3 < width)
-            stream_group<U, true, E>(cs.best[k], p0, ld, 4, list, m, lo.r, lo.P);
+            stream_group<U, true, E, NT>(cs.best[k], p0, ld, 4, list, m, lo.r, lo.P);
         else
-            stream_group<U, false, E>(cs.best[k], p0, ld, min(4, width - v0), list, m, lo.r, lo.P);
+            stream_group<U, false, E, NT>(cs.best[k], p0, ld, min(4, width - v0), list, m, lo.r, lo.P);
     }
 }
 

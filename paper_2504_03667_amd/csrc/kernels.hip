@@ -306,7 +306,7 @@ __device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const 
 // Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
 // entries (double-buffered by barrier parity).  Returns false if a barrier
 // wait timed out.  `trace` (may be null) receives rank 0's round trace.
-template <int T, int G, int U, typename E>
+template <int T, int G, int U, typename E, bool NT = false>
 __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                            int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
                            int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
@@ -349,7 +349,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 reset_best(cs);
                 if (threadIdx.x == 0) sh.list[0] = (int32_t)pu0;
                 __syncthreads();
-                stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
                 merge_partitions<T, G>(cs, lo, sh.mrg);
                 if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, owner_bit(lo, (int64_t)pu0 - col0, width), pred);
                 else reset_best(cs);
@@ -383,7 +383,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
             bucket = owner_bit(lo, (int64_t)u0 - col0, width);
             if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
             __syncthreads();
-            stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+            stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
             const uint32_t c = ((int)threadIdx.x < nwg && (uint32_t)(rec.key >> 32) == d) ? rec.count : 0u;
@@ -400,7 +400,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 sh.list[threadIdx.x] = nxt;
                 __syncthreads();
                 if (e0 + kCap < M) nxt = gather_entry<T>(sh, rl, nwg, S, e0 + kCap, M);
-                stream_rows<G, U, E>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
+                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
                 __syncthreads();
             }
         }
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                                             Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
-    solve_gang<T, G, U, int32_t>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
+    solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
                         blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl);
     finish_launch(ctl, st, blockIdx.x == 0);
 }
