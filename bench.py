@@ -217,6 +217,29 @@ def bench_served(sp, torch, gen, args):
     return res
 
 
+def cpu_throughput(gen):
+    """Independent oracle solves spread over every host core (one solve per thread), on
+    samples of the batched and served instance sets: CPU solves/s for context."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    cores = os.cpu_count() or 1
+    out = {"cores": cores, "kind": "oracle"}
+    for name, wl, pairs in (("batched", gen.workload_batched(), None), ("served", gen.workload_serving(n_queries=400), None)):
+        pairs = wl.instances if wl.instances else [(q.graph, q.src) for q in wl.queries]
+        rng = np.random.default_rng(7)
+        pick = [pairs[i] for i in rng.permutation(len(pairs))[:2 * cores]]
+        need = sorted({g for g, _ in pick})
+        host = {g: gen.dense_host(wl.graphs[g]) for g in need}
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda gs: oracle.dijkstra(host[gs[0]], gs[1]), pick))
+        dt = time.perf_counter() - t0
+        out[name] = {"solves_per_s": round(len(pick) / dt, 2), "sample": "%d instances drawn from the set" % len(pick),
+                     "seconds": round(dt, 2)}
+        del host
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -310,6 +333,10 @@ def main():
         # ---- served: 32 resident graphs, Poisson trace, continuous batching --------
         extra["served"] = bench_served(sp, torch, gen, args)
         torch.cuda.empty_cache()
+
+        # ---- CPU oracle over all host cores on samples of the batched / served sets --
+        if not args.skip_cpu:
+            extra["cpu_batched_served"] = cpu_throughput(gen)
 
     # ---- CPU oracle on a bounded sample of the headline workload -----------------
     cpu = None

@@ -167,6 +167,35 @@ int sssp_batch_plan_status(sssp_batch_plan* plan, void* stream, int32_t* status,
 /* Waits for the plan's last launch, then frees it and its compact copies. */
 int sssp_batch_plan_destroy(sssp_batch_plan* plan);
 
+/*
+ * Edge list -> dense matrix (the input step of Section III): W (device, n rows
+ * of stride ld) is set to 0 on the diagonal and INT32_MAX elsewhere, then each
+ * edge (eu[e], ev[e], ew[e]) (device arrays of m entries) is written at
+ * W[u][v], and also at W[v][u] unless `directed`.  A repeated edge keeps its
+ * smallest weight; a self-loop leaves the diagonal at 0; an edge with an
+ * endpoint outside [0, n) or a weight outside [0, INT32_MAX) is skipped and
+ * counted in *bad_edges (may be NULL).  Synchronises `stream`.
+ */
+int sssp_edges_to_dense(const int32_t* eu, const int32_t* ev, const int32_t* ew, int64_t m, int32_t n,
+                        int32_t directed, int32_t* W, int64_t ld, int64_t* bad_edges, void* stream);
+
+/*
+ * Hop counts of the shortest-path tree a solve returned (device arrays of n):
+ * hops[v] = edges on the pred chain from the source to v, 0 at the source,
+ * -1 where dist[v] is INT32_MAX.  Pointer jumping, O(log n) passes;
+ * asynchronous.  pred must come from a solve (a forest rooted at the source).
+ */
+int sssp_hops(const int32_t* pred, const int32_t* dist, int32_t n, int32_t* hops, void* stream);
+
+/*
+ * Paths out of pred: for each of `count` targets (device array), writes the
+ * hops[t] + 1 vertices source ... t into out[offsets[i] ...] (device arrays;
+ * offsets are the caller's, e.g. an exclusive prefix sum of hops[t] + 1).
+ * Unreachable or out-of-range targets write nothing.  Asynchronous.
+ */
+int sssp_paths(const int32_t* pred, const int32_t* hops, int32_t n, const int32_t* targets, int32_t count,
+               const int64_t* offsets, int32_t* out, void* stream);
+
 /* Weight range of a device matrix (synchronous): *min_w over all entries, *max_finite_w
  * over entries other than INT32_MAX.  *min_w < 0 means the input violates Dijkstra's
  * precondition. */

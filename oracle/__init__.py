@@ -51,6 +51,11 @@ def lib():
         L.oracle_closed_form_pred.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P,
                                               ctypes.c_int32]
         L.oracle_closed_form_pred.restype = ctypes.c_int
+        L.oracle_edges_to_dense.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
+                                            ctypes.c_int64]
+        L.oracle_edges_to_dense.restype = ctypes.c_int64
+        L.oracle_hops.argtypes = [P, P, ctypes.c_int32, P]
+        L.oracle_hops.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -134,3 +139,25 @@ def closed_form_pred(W, dist, threads=None):
                                      pred.ctypes.data, _threads(threads)) != 0:
         raise ValueError("bad arguments")
     return pred
+
+
+def edges_to_dense(eu, ev, ew, n, directed=False):
+    """The edge list written into an n x n matrix; returns (W, skipped edges)."""
+    eu = np.ascontiguousarray(eu, np.int32)
+    ev = np.ascontiguousarray(ev, np.int32)
+    ew = np.ascontiguousarray(ew, np.int32)
+    W = np.empty((n, n), np.int32)
+    bad = lib().oracle_edges_to_dense(eu.ctypes.data, ev.ctypes.data, ew.ctypes.data, eu.size, n,
+                                      int(bool(directed)), W.ctypes.data, n)
+    if bad < 0:
+        raise ValueError("bad arguments")
+    return W, int(bad)
+
+
+def hops(pred, dist):
+    pred = np.ascontiguousarray(pred, np.int32)
+    dist = np.ascontiguousarray(dist, np.int32)
+    h = np.empty(pred.size, np.int32)
+    if lib().oracle_hops(pred.ctypes.data, dist.ctypes.data, pred.size, h.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return h

@@ -306,3 +306,43 @@ int oracle_closed_form_pred(const int32_t* W, int64_t ld, int32_t n, const int32
     free(order);
     return 0;
 }
+
+/* ---------------- input and output steps ---------------- */
+
+/*
+ * The input step of Section III: an edge list written into the adjacency
+ * matrix.  Diagonal 0, INT32_MAX elsewhere, then each edge (u, v, w) at
+ * W[u][v] and, for an undirected graph, at W[v][u]; a repeated edge keeps its
+ * smallest weight and a self-loop leaves the diagonal at 0 (readings: the
+ * paper does not say).  Edges with an endpoint outside [0, n) or a weight
+ * outside [0, INT32_MAX) are skipped; returns how many, or -1 on bad arguments.
+ */
+int64_t oracle_edges_to_dense(const int32_t* eu, const int32_t* ev, const int32_t* ew, int64_t m, int32_t n,
+                              int32_t directed, int32_t* W, int64_t ld)
+{
+    if (!W || n < 1 || ld < n || m < 0) return -1;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n; ++j) W[(int64_t)i * ld + j] = (i == j) ? 0 : OR_INF;
+    int64_t bad = 0;
+    for (int64_t e = 0; e < m; ++e) {
+        int32_t u = eu[e], v = ev[e], w = ew[e];
+        if (u < 0 || u >= n || v < 0 || v >= n || w < 0 || w == OR_INF) { ++bad; continue; }
+        if (u == v) continue;
+        if (w < W[(int64_t)u * ld + v]) W[(int64_t)u * ld + v] = w;
+        if (!directed && w < W[(int64_t)v * ld + u]) W[(int64_t)v * ld + u] = w;
+    }
+    return bad;
+}
+
+/* Edges on the pred chain from the source to v, by walking it; -1 if unreachable. */
+int oracle_hops(const int32_t* pred, const int32_t* dist, int32_t n, int32_t* hops)
+{
+    if (!pred || !dist || !hops || n < 1) return -1;
+    for (int32_t v = 0; v < n; ++v) {
+        if (dist[v] == OR_INF) { hops[v] = -1; continue; }
+        int32_t h = 0, x = v;
+        while (pred[x] >= 0 && h <= n) { x = pred[x]; ++h; }
+        hops[v] = h;
+    }
+    return 0;
+}

@@ -119,6 +119,9 @@ def lib():
         L.sssp_dense_validate.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
         L.sssp_server_add_graph_ex.argtypes = [P, P, I64, I32, U32, ctypes.POINTER(I32)]
         L.sssp_server_graph_elem.argtypes = [P, I32, ctypes.POINTER(I32)]
+        L.sssp_edges_to_dense.argtypes = [P, P, P, I64, I32, I32, P, I64, ctypes.POINTER(I64), P]
+        L.sssp_hops.argtypes = [P, P, I32, P, P]
+        L.sssp_paths.argtypes = [P, P, I32, P, I32, P, P, P]
         L.sssp_single_max_n.restype = I32
         L.sssp_server_now_ns.restype = I64
         L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
@@ -293,6 +296,50 @@ class BatchPlan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _ptr64(t, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int64:
+        raise TypeError("%s must be an int64 tensor on the GPU" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sssp_edges_to_dense(eu, ev, ew, n, W, ld=None, directed=False, stream=None):
+    """Writes the edge list (int32 device tensors) into W; returns the number of skipped edges."""
+    m = eu.numel()
+    if ev.numel() != m or ew.numel() != m:
+        raise ValueError("edge arrays differ in length")
+    bad = ctypes.c_int64(0)
+    nul = ctypes.c_void_p(None)
+    _check(lib().sssp_edges_to_dense(_ptr(eu, "eu") if m else nul, _ptr(ev, "ev") if m else nul,
+                                     _ptr(ew, "ew") if m else nul, m, n, int(bool(directed)), _ptr(W, "W"),
+                                     W.stride(0) if ld is None else ld, ctypes.byref(bad), _stream(stream)))
+    return bad.value
+
+
+def sssp_hops(pred, dist, hops, stream=None):
+    return _check(lib().sssp_hops(_ptr(pred, "pred"), _ptr(dist, "dist"), pred.numel(), _ptr(hops, "hops"),
+                                  _stream(stream)))
+
+
+def sssp_paths(pred, hops, targets, offsets, out, stream=None):
+    return _check(lib().sssp_paths(_ptr(pred, "pred"), _ptr(hops, "hops"), pred.numel(), _ptr(targets, "targets"),
+                                   targets.numel(), _ptr64(offsets, "offsets"), _ptr(out, "out"),
+                                   _stream(stream)))
+
+
+def paths(pred, dist, targets):
+    """Shortest paths source ... t for each target, as a list of int32 device tensors."""
+    n = pred.numel()
+    hops = torch.empty(n, dtype=torch.int32, device=pred.device)
+    sssp_hops(pred, dist, hops)
+    t = torch.as_tensor(targets, dtype=torch.int32, device=pred.device)
+    lens = torch.where(hops[t.long()] >= 0, hops[t.long()] + 1, torch.zeros_like(t)).to(torch.int64)
+    offsets = torch.cumsum(lens, 0) - lens
+    out = torch.full((int(lens.sum().item()) + 1,), -1, dtype=torch.int32, device=pred.device)
+    sssp_paths(pred, hops, t, offsets, out)
+    o, l_ = offsets.tolist(), lens.tolist()
+    return [out[o[i]:o[i] + l_[i]] for i in range(len(o))]
 
 
 # ---- convenience wrappers (allocate outputs, return tensors) ----
