@@ -211,8 +211,33 @@ def bench_served(sp, torch, gen, args):
         torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     res["plain"] = {"queries": k, "solves_per_s": round(k / tp, 1)}
+    # the same prefix replayed at its scheduled arrivals, one solve per launch: the plain
+    # path cannot keep up with 2000 queries/s, so its latency grows along the trace
+    lat = []
+    t0 = time.perf_counter() + 0.002
+    for q, (d, p) in list(zip(wl.queries, outs))[:k]:
+        arrive = t0 + q.arrival_s
+        while time.perf_counter() < arrive:
+            pass
+        W = mats[q.graph]
+        sp.sssp_dense_solve_ex(W, W.stride(0), W.shape[0], q.src, d, p, 0)
+        torch.cuda.current_stream().synchronize()
+        lat.append((time.perf_counter() - arrive) * 1e6)
+    res["plain"]["replay"] = {"queries": k, "p50_us": round(percentile(lat, 50), 1),
+                              "p99_us": round(percentile(lat, 99), 1), "max_us": round(max(lat), 1)}
+    # literal mode of the plain path (one vertex per step, as Algorithm 1 is printed)
+    kl = min(30, len(wl.queries))
+    t0 = time.perf_counter()
+    for q, (d, p) in list(zip(wl.queries, outs))[:kl]:
+        W = mats[q.graph]
+        sp.sssp_dense_solve_ex(W, W.stride(0), W.shape[0], q.src, d, p, sp.SSSP_FLAG_LITERAL)
+        torch.cuda.current_stream().synchronize()
+    tl = time.perf_counter() - t0
+    res["plain_literal"] = {"queries": kl, "solves_per_s": round(kl / tl, 2)}
     for name in ("server_int32", "server_compact"):
         res[name]["saturation_speedup_vs_plain"] = round(res[name]["saturation"]["solves_per_s"] / (k / tp), 2)
+        res[name]["saturation_speedup_vs_plain_literal"] = round(
+            res[name]["saturation"]["solves_per_s"] / (kl / tl), 1)
     del mats, outs
     return res
 
@@ -222,12 +247,21 @@ def cpu_throughput(gen):
     samples of the batched and served instance sets: CPU solves/s for context."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
-    cores = os.cpu_count() or 1
-    out = {"cores": cores, "kind": "oracle"}
-    for name, wl, pairs in (("batched", gen.workload_batched(), None), ("served", gen.workload_serving(n_queries=400), None)):
+    # the host share of one GPU is 16 cores, whatever the machine has in total
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"cores": cores, "cpu_model": model, "kind": "oracle"}
+    for name, wl, per_core in (("batched", gen.workload_batched(), 32), ("served", gen.workload_serving(n_queries=400), 12)):
         pairs = wl.instances if wl.instances else [(q.graph, q.src) for q in wl.queries]
         rng = np.random.default_rng(7)
-        pick = [pairs[i] for i in rng.permutation(len(pairs))[:2 * cores]]
+        pick = [pairs[i] for i in rng.permutation(len(pairs))[:per_core * cores]]
         need = sorted({g for g, _ in pick})
         host = {g: gen.dense_host(wl.graphs[g]) for g in need}
         t0 = time.perf_counter()
@@ -310,9 +344,13 @@ def main():
                 if g2 != gi:
                     continue
                 rr = timed_solves(sp, torch, Wm, src, 10, 2)
+                kms = percentile(rr["kernel_ms"], 50)
+                gbps = (4.0 * g.n * rr["stats"][1] + 8.0 * g.n) / (kms * 1e-3) / 1e9
                 med.append({"directed": g.directed, "src": src, "ms_per_solve": round(rr["ms_per_step"], 4),
-                            "rows_relaxed": rr["stats"][1], "rounds": rr["stats"][0],
-                            "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3)})
+                            "kernel_ms_median": round(kms, 4), "rows_relaxed": rr["stats"][1],
+                            "rounds": rr["stats"][0],
+                            "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3),
+                            "algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)})
             del Wm
         extra["n16384"] = med
         torch.cuda.empty_cache()
@@ -320,10 +358,15 @@ def main():
         # ---- n = 1024, p = 0.1: latency of one solve ------------------------------
         g1 = gen.workload_single_small().graphs[0]
         W1 = gen.dense_device(g1)
-        rr = timed_solves(sp, torch, W1, 0, 200, 10)
-        extra["n1024"] = {"median_us": round(1e3 * percentile(rr["kernel_ms"], 50), 2),
-                          "p99_us": round(1e3 * percentile(rr["kernel_ms"], 99), 2),
-                          "rounds": rr["stats"][0]}
+        c1 = {}
+        for mode, flags, reps in (("single_workgroup", 0, 1000), ("whole_gpu", sp.SSSP_FLAG_GRID, 200)):
+            rr = timed_solves(sp, torch, W1, 0, reps, 10, flags=flags)
+            med_us = 1e3 * percentile(rr["kernel_ms"], 50)
+            c1[mode] = {"reps": reps, "median_us": round(med_us, 2),
+                        "p99_us": round(1e3 * percentile(rr["kernel_ms"], 99), 2),
+                        "rounds": rr["stats"][0], "rows_relaxed": rr["stats"][1],
+                        "entries_per_s": g1.n * rr["stats"][1] / (med_us * 1e-6)}
+        extra["n1024"] = c1
         del W1
 
         # ---- batched: 320 instances in one launch vs one solve per launch ---------

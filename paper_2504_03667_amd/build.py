@@ -43,18 +43,24 @@ def build(verbose=False):
     return SO
 
 
-if __name__ == "__main__":
-    build(verbose=True)
+# The files the whole-GPU solve (its kernel, launch shape and flags) is built from;
+# a profile taken of that kernel stays valid while none of them changes.
+GRID_KERNEL_FILES = ("kernels.hip", "engine.h", "sssp_internal.h", "api.cpp")
 
 
-def source_hash():
-    """Short hash of the kernel and ABI sources (ties profiles to the code they measured)."""
+def source_hash(files=GRID_KERNEL_FILES):
+    """Short hash of the sources the whole-GPU solve is built from, plus the public
+    header and this build script's compiler flags (ties profiles to the code they measured)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(files):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     with open(os.path.join(ROOT, "include", "sssp.h"), "rb") as f:
         h.update(f.read())
+    h.update(" ".join(f for f in FLAGS if os.sep not in f).encode())  # flags, not paths
     return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    build(verbose=True)
