@@ -56,6 +56,9 @@ def lib():
         L.oracle_edges_to_dense.restype = ctypes.c_int64
         L.oracle_hops.argtypes = [P, P, ctypes.c_int32, P]
         L.oracle_hops.restype = ctypes.c_int
+        L.oracle_label_correcting.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_label_correcting.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -161,3 +164,16 @@ def hops(pred, dist):
     if lib().oracle_hops(pred.ctypes.data, dist.ctypes.data, pred.size, h.ctypes.data) != 0:
         raise ValueError("bad arguments")
     return h
+
+
+def label_correcting(W, src):
+    """Synchronous label-correcting sweeps (the paper's CUDA method): returns
+    (dist, sweeps, rows relaxed)."""
+    W, ld = _mat(W)
+    n = W.shape[0]
+    dist = np.empty(n, np.int32)
+    sw, rows = ctypes.c_int64(), ctypes.c_int64()
+    if lib().oracle_label_correcting(W.ctypes.data, ld, n, src, dist.ctypes.data, ctypes.byref(sw),
+                                     ctypes.byref(rows)) != 0:
+        raise ValueError("bad arguments")
+    return dist, int(sw.value), int(rows.value)

@@ -18,6 +18,9 @@
  *   oracle_closed_form_pred  pred characterised without running the loop;
  *                          equals Algorithm 1's pred whenever every
  *                          off-diagonal weight is >= 1.
+ *   oracle_label_correcting  the paper's CUDA method (Algorithms 3 and 4) as
+ *                          synchronous sweeps over the changed vertices:
+ *                          dist, the number of sweeps and the rows relaxed.
  * All arithmetic on path lengths is exact (int64).
  */
 #include <stdint.h>
@@ -304,6 +307,61 @@ int oracle_closed_form_pred(const int32_t* W, int64_t ld, int32_t n, const int32
     for (int t = 0; t < nt; ++t)
         if (tid[t]) pthread_join(tid[t], NULL);
     free(order);
+    return 0;
+}
+
+/*
+ * Label-correcting sweeps (Section III-C: Algorithm 3 repeats the kernel of
+ * Algorithm 4 until no dist changes; each kernel thread relaxes the row of its
+ * vertex with dist[tid] + Adj[tid][v] < dist[v]).  Taken here in synchronous
+ * form: a sweep relaxes the row of every vertex whose dist changed in the
+ * previous sweep (the source in the first), each with the dist it had when
+ * the sweep began, and all improvements take effect when the sweep ends.
+ * Rows of vertices whose dist did not change cannot improve anything, which is
+ * why Algorithm 4's full sweep can be narrowed to them.  Stops after a sweep
+ * that changes nothing.  dist only (pred is not part of this method's steps);
+ * *sweeps and *rows (both may be NULL) get the number of sweeps and the total
+ * of rows relaxed.  Returns 0, or -1 on bad arguments / no memory.
+ */
+int oracle_label_correcting(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
+                            int64_t* sweeps, int64_t* rows)
+{
+    if (!W || !dist || n < 1 || ld < n || src < 0 || src >= n) return -1;
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* next = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    unsigned char* changed = (unsigned char*)malloc((size_t)n);
+    if (!d || !next || !changed) { free(d); free(next); free(changed); return -1; }
+    for (int32_t v = 0; v < n; ++v) { d[v] = OR_INF; changed[v] = 0; }
+    d[src] = 0;
+    changed[src] = 1;
+    int64_t nsweeps = 0, nrows = 0;
+    for (;;) {
+        int any = 0;
+        for (int32_t v = 0; v < n; ++v) any |= changed[v];
+        if (!any) break;
+        ++nsweeps;
+        memcpy(next, d, sizeof(int64_t) * (size_t)n);
+        for (int32_t u = 0; u < n; ++u) {
+            if (!changed[u]) continue;
+            ++nrows;
+            const int32_t* row = W + (int64_t)u * ld;
+            for (int32_t v = 0; v < n; ++v) {
+                if (row[v] == OR_INF) continue;
+                int64_t c = d[u] + (int64_t)row[v];
+                if (c < next[v]) next[v] = c;
+            }
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            changed[v] = next[v] < d[v];
+            d[v] = next[v];
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) dist[v] = d[v] >= OR_INF ? OR_INF : (int32_t)d[v];
+    if (sweeps) *sweeps = nsweeps;
+    if (rows) *rows = nrows;
+    free(d);
+    free(next);
+    free(changed);
     return 0;
 }
 
