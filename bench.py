@@ -105,6 +105,27 @@ def median_launch_ms(torch, fn, reps=7):
     return sorted(ts)[len(ts) // 2] * 1e3
 
 
+def bench_many_levels(sp, torch, gen):
+    """Graphs whose shortest paths take hundreds of distinct distances (sparse, weights
+    in [1, 1000], like the sparse end of the served set): the Dijkstra rounds pay one
+    barrier per distance, the label-correcting sweeps one per sweep."""
+    out = []
+    for n, p, seed in ((4096, 0.002, 11), (8192, 0.001, 12), (16384, 0.0005, 13), (32768, 0.0005, 14)):
+        g = gen.GraphSpec(n, p, 1, 1000, gen.SEED_BASE + 100 + seed)
+        W = gen.dense_device(g)
+        row = {"n": n, "p": p, "weights": [1, 1000]}
+        for name, flags in (("dijkstra", 0), ("dijkstra_one_workgroup", sp.SSSP_FLAG_SINGLE),
+                            ("label_correcting", sp.SSSP_FLAG_LABEL_CORRECTING)):
+            if flags == sp.SSSP_FLAG_SINGLE and n > sp.sssp_single_max_n():
+                continue
+            r = timed_solves(sp, torch, W, 0, 5, 1, flags=flags)
+            row[name] = {"ms_per_solve": round(r["ms_per_step"], 3), "rounds": r["stats"][0],
+                         "rows_streamed": r["stats"][1]}
+        out.append(row)
+        del W
+    return out
+
+
 def bench_batched(sp, torch, gen):
     """256 sources on one n=8192 graph plus 64 graphs: one-shot launch, autotuned plans
     (int32 and exact compact copies, replayed as a hipGraph) and one solve per launch."""
@@ -178,15 +199,33 @@ def bench_served(sp, torch, gen, args):
                     tickets.append(srv.submit(gids[q.graph], q.src, d, p))
                 for t in tickets:
                     srv.wait(t, timeout_s=300)
-                lat, t_end, bad = [], 0, 0
+                lat, svc, t_end, bad = [], [], 0, 0
                 for q, t in zip(wl.queries, tickets):
                     inf = srv.info(t)
                     bad += inf["status"] & 3
                     lat.append((inf["t_done_ns"] - (t0 + int(q.arrival_s * 1e9))) / 1e3)
+                    svc.append((inf["t_done_ns"] - inf["t_admit_ns"]) / 1e3)
                     t_end = max(t_end, inf["t_done_ns"])
                 r["replay"] = {"p50_us": round(percentile(lat, 50), 1), "p99_us": round(percentile(lat, 99), 1),
                                "mean_us": round(sum(lat) / len(lat), 1), "max_us": round(max(lat), 1),
+                               "admitted_to_done_p50_us": round(percentile(svc, 50), 1),
+                               "admitted_to_done_p99_us": round(percentile(svc, 99), 1),
                                "solves_per_s": round(len(tickets) / ((t_end - t0) / 1e9), 1), "bad_status": bad}
+                # one query per graph with the server otherwise idle: the latency floor
+                alone = []
+                for gi in range(len(wl.graphs)):
+                    q = next((q for q in wl.queries if q.graph == gi), None)
+                    if q is None:
+                        continue
+                    d, p = outs[wl.queries.index(q)]
+                    t = srv.submit(gids[gi], q.src, d, p)
+                    srv.wait(t, timeout_s=120)
+                    inf = srv.info(t)
+                    alone.append(((inf["t_done_ns"] - inf["t_submit_ns"]) / 1e3, gi, inf["rounds"], inf["parts"]))
+                alone.sort()
+                r["alone"] = {"graphs": len(alone), "median_us": round(alone[len(alone) // 2][0], 1),
+                              "slowest": [{"us": round(a, 1), "n": wl.graphs[gi].n, "p": round(wl.graphs[gi].p, 5),
+                                           "rounds": rd, "parts": pt} for a, gi, rd, pt in alone[-4:]]}
             # saturation: every query released at once
             ts = sp.sssp_server_now_ns()
             tickets = [srv.submit(gids[q.graph], q.src, d, p) for q, (d, p) in zip(wl.queries, outs)]
@@ -346,13 +385,21 @@ def main():
                 rr = timed_solves(sp, torch, Wm, src, 10, 2)
                 kms = percentile(rr["kernel_ms"], 50)
                 gbps = (4.0 * g.n * rr["stats"][1] + 8.0 * g.n) / (kms * 1e-3) / 1e9
+                lc = timed_solves(sp, torch, Wm, src, 10, 2, flags=sp.SSSP_FLAG_LABEL_CORRECTING)
                 med.append({"directed": g.directed, "src": src, "ms_per_solve": round(rr["ms_per_step"], 4),
                             "kernel_ms_median": round(kms, 4), "rows_relaxed": rr["stats"][1],
                             "rounds": rr["stats"][0],
                             "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3),
-                            "algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4)})
+                            "algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4),
+                            "label_correcting": {"ms_per_solve": round(lc["ms_per_step"], 4),
+                                                 "sweeps": lc["stats"][0], "rows_streamed": lc["stats"][1]}})
+                del lc
             del Wm
         extra["n16384"] = med
+        torch.cuda.empty_cache()
+
+        # ---- sparse graphs with wide weights: Dijkstra rounds vs label-correcting ----
+        extra["many_levels"] = bench_many_levels(sp, torch, gen)
         torch.cuda.empty_cache()
 
         # ---- n = 1024, p = 0.1: latency of one solve ------------------------------

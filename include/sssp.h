@@ -53,7 +53,8 @@ extern "C" {
 /* asynchronous status bits (sssp_last_status) */
 #define SSSP_STATUS_TIMEOUT 1         /* a grid barrier gave up waiting: results invalid */
 #define SSSP_STATUS_NEG_WEIGHT 2      /* a negative weight was seen: precondition violated */
-#define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps (informational) */
+#define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps, or sent a
+                                         label-correcting solve back to the Dijkstra rounds (informational) */
 
 /* flags for sssp_dense_solve_ex / batched calls */
 #define SSSP_FLAG_LITERAL 1u  /* settle one vertex per round: Algorithm 1 exactly as printed */
@@ -61,6 +62,16 @@ extern "C" {
 #define SSSP_FLAG_GRID 4u     /* force the persistent whole-GPU kernel */
 #define SSSP_FLAG_COMPACT 8u  /* plans and servers: stream an exact uint8/uint16 copy of each graph
                                  whose weights all fit (built once, owned by the plan or server) */
+#define SSSP_FLAG_LABEL_CORRECTING 16u
+/* sssp_dense_solve_ex: the label-correcting method of the paper's CUDA design
+ * (Section III-C, Algorithms 3 and 4), made deterministic: sweeps relax the rows
+ * of the vertices whose dist changed in the previous sweep until none changes,
+ * then one pass over the reachable rows sets pred[v] to the u of smallest
+ * (dist[u], u) with dist[u] + W[u][v] == dist[v].  Same dist and pred as
+ * Algorithm 1: when that pass finds a tight zero-weight edge the launch solves
+ * again with the Dijkstra rounds (SSSP_STATUS_ZERO_FALLBACK).  Runs on the
+ * whole-GPU grid (SSSP_FLAG_SINGLE: one workgroup); not with SSSP_FLAG_LITERAL.
+ * Stats: ROUNDS = sweeps, SETTLED = rows streamed (frontiers plus the pred pass). */
 
 /* statistics of a finished launch (sssp_last_status `stats`, 4 entries) */
 #define SSSP_STAT_ROUNDS 0     /* rounds (one bucket of equal-dist vertices, or one vertex, each) */

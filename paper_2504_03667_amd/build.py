@@ -11,7 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libsssp.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp", "batch.cpp", "paths.hip"]
+SOURCES = ["kernels.hip", "lc.hip", "api.cpp", "server.cpp", "batch.cpp", "paths.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -45,7 +45,7 @@ def build(verbose=False):
 
 # The files the whole-GPU solve (its kernel, launch shape and flags) is built from;
 # a profile taken of that kernel stays valid while none of them changes.
-GRID_KERNEL_FILES = ("kernels.hip", "engine.h", "sssp_internal.h", "api.cpp")
+GRID_KERNEL_FILES = ("kernels.hip", "solve.h", "engine.h", "sssp_internal.h", "api.cpp")
 
 
 def source_hash(files=GRID_KERNEL_FILES):

@@ -48,6 +48,8 @@ struct Scratch {
     size_t pubs_cap = 0;
     int32_t* lists = nullptr;
     size_t lists_cap = 0;
+    uint64_t* lists64 = nullptr;  // label-correcting frontier lists
+    size_t lists64_cap = 0;
     bool launched = false;
 };
 
@@ -163,6 +165,9 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
     if (rc) return rc;
     if ((flags & SSSP_FLAG_SINGLE) && (flags & SSSP_FLAG_GRID))
         return fail(SSSP_EINVAL, "SSSP_FLAG_SINGLE and SSSP_FLAG_GRID are exclusive");
+    if ((flags & SSSP_FLAG_LABEL_CORRECTING) && (flags & SSSP_FLAG_LITERAL))
+        return fail(SSSP_EINVAL, "SSSP_FLAG_LABEL_CORRECTING and SSSP_FLAG_LITERAL are exclusive");
+    const bool lc = (flags & SSSP_FLAG_LABEL_CORRECTING) != 0;
     std::lock_guard<std::mutex> lk(g_mu);
     Scratch* sc = nullptr;
     DeviceInfo di;
@@ -170,8 +175,8 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
     if (rc) return rc;
     SolveArgs a{W, ld, n, src, dist, pred, flags & SSSP_FLAG_LITERAL, sc->ctl};
     if (aligned16(W) && ld % 4 == 0) a.flags |= kFlagVec;
-    const bool single = (flags & SSSP_FLAG_SINGLE) ||
-                        (!(flags & SSSP_FLAG_GRID) && n <= single_crossover());
+    const bool single = !lc && ((flags & SSSP_FLAG_SINGLE) ||
+                                (!(flags & SSSP_FLAG_GRID) && n <= single_crossover()));
     hipError_t e;
     if (single) {
         if (n > max_single_n())
@@ -184,11 +189,12 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         // slice width: about 128 columns (512 B of each row) per workgroup by default, as
         // many workgroups as fit; wider slices when n outgrows the grid
         int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 127) / 128);
+        if (lc && (flags & SSSP_FLAG_SINGLE)) want = 1;
         int S = (int)(((int64_t)n + want - 1) / want);
         S = (S + 3) & ~3;
         if (S > max_grid_slice()) S = max_grid_slice();
         int nwg = (int)(((int64_t)n + S - 1) / S);
-        e = (hipError_t)grid_occupancy(S, &per_cu);
+        e = (hipError_t)(lc ? lc_occupancy(S, &per_cu) : grid_occupancy(S, &per_cu));
         if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
         const int cap = std::min(1024, per_cu * di.cus);
         if (nwg > cap) {
@@ -201,10 +207,17 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         }
         rc = ensure(sc, sc->pubs, sc->pubs_cap, 2 * (size_t)nwg, "exchange records");
         if (rc) return rc;
-        rc = ensure(sc, sc->lists, sc->lists_cap, 2 * (size_t)nwg * S, "bucket lists");
-        if (rc) return rc;
-        e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, plain_grid_launch(), stream);
-        if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
+        if (lc) {
+            rc = ensure(sc, sc->lists64, sc->lists64_cap, 2 * (size_t)nwg * S, "frontier lists");
+            if (rc) return rc;
+            e = launch_lc(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists64, plain_grid_launch(), stream);
+            if (e != hipSuccess) return hip_fail(e, "cooperative launch(label-correcting solve)");
+        } else {
+            rc = ensure(sc, sc->lists, sc->lists_cap, 2 * (size_t)nwg * S, "bucket lists");
+            if (rc) return rc;
+            e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, plain_grid_launch(), stream);
+            if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
+        }
     }
     sc->launched = true;
     return SSSP_OK;

@@ -24,123 +24,10 @@
 #include <stdint.h>
 
 #include "engine.h"
+#include "solve.h"
 #include "sssp_internal.h"
 
 namespace sssp {
-
-constexpr int kCap = 1024;  // bucket rows staged in LDS per chunk
-
-template <int T>
-struct SharedSolve {
-    Red<T> red;
-    int32_t list[kCap];
-    uint64_t mrg[4 * T];
-    uint32_t pre[T];
-    uint32_t cnt[T];
-    int32_t item;
-    uint32_t flag;
-};
-
-struct SolveStats {
-    unsigned long long rounds, settled, fallbacks, barriers;
-    uint32_t status;
-};
-
-// The workgroup's LDS state, at namespace scope so that solver variants compiled
-// as separate functions still address it as LDS.
-template <int T>
-__shared__ SharedSolve<T> g_sh;
-
-// bit of local column v (0 <= v < width) if this thread owns it, else 0
-__device__ __forceinline__ uint32_t owner_bit(const Layout& lo, int64_t v, int width) {
-    if (v < 0 || v >= width || lo.r != 0) return 0;
-    const int64_t gi = v >> 2;
-    if (gi % lo.L != lo.c) return 0;
-    const int k = (int)(gi / lo.L);
-    return 1u << (4 * k + (int)(v & 3));
-}
-
-// ---------------------------------------------------------------------------
-// One workgroup, whole row.
-// ---------------------------------------------------------------------------
-template <int T, int G, int U, typename E>
-__device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
-                             int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec,
-                             bool literal, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
-    const Layout lo = make_layout<T>(n);
-    Cols<G> cs;
-    init_cols(cs, lo, 0, n, src, pred);
-    for (;;) {
-        // a2/a3: argmin over unvisited vertices, lowest index on ties
-        uint64_t key = local_argmin(cs, lo, 0);
-        uint32_t none = 0;
-        block_min_or<T>(key, none, sh.red);
-        const uint32_t d = (uint32_t)(key >> 32);
-        if (key == kNoKey || d >= kInf) break;  // a4: nothing reachable is left
-        const uint32_t u0 = (uint32_t)key;
-        const long long t_round = wall_clock64();
-        uint32_t bucket;
-        uint32_t M;
-        if (literal) {
-            bucket = owner_bit(lo, u0, n);
-            M = 1;
-            if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
-            __syncthreads();
-            stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
-        } else {
-            bucket = bucket_mask(cs, d);
-            const uint32_t base = block_excl_scan<T>(__popc(bucket), M, sh.red);
-            for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
-                uint32_t rank = base;
-#pragma unroll
-                for (int k = 0; k < G; ++k)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (bucket >> (4 * k + j) & 1u) {
-                            if (rank >= e0 && rank < e0 + kCap)
-                                sh.list[rank - e0] = local_col(lo, k, j);
-                            ++rank;
-                        }
-                __syncthreads();
-                stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
-                __syncthreads();
-            }
-        }
-        merge_partitions<T, G>(cs, lo, sh.mrg);
-        ++st.rounds;
-        if (trace && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
-            trace->trace_t[st.rounds - 1] = t_round;
-            trace->trace_m[st.rounds - 1] = M;
-        }
-        if (!literal) {
-            uint32_t z = lo.r == 0 ? zero_hazard(cs, d) : 0u;
-            uint64_t dummy = kNoKey;
-            block_min_or<T>(dummy, z, sh.red);
-            if (z) {
-                // discard the fused round; settle only u0 (one literal step)
-                ++st.fallbacks;
-                st.status |= kStatusZeroFallback;
-                reset_best(cs);
-                if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
-                __syncthreads();
-                stream_rows<G, U, E>(cs, lo, W, ld, 0, n, vec, sh.list, 1);
-                merge_partitions<T, G>(cs, lo, sh.mrg);
-                bucket = owner_bit(lo, u0, n);
-                M = 1;
-            }
-        }
-        // a5/a6: settle the bucket and relax
-        if (lo.r == 0) st.status |= commit_fused(cs, lo, 0, d, bucket, pred);
-        else reset_best(cs);
-        st.settled += M;
-    }
-    write_dist(cs, lo, 0, n, dist);  // a8
-    if (trace && threadIdx.x == 0) {
-        const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
-        trace->trace_t[nr] = wall_clock64();
-        trace->trace_n = (uint32_t)nr;
-    }
-}
 
 template <int T, int G, int U>
 __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int64_t ld, int32_t n,
@@ -161,285 +48,6 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
         ctl->last[kStatBarriers] = 0;
         ctl->status = s;
     }
-}
-
-// ---------------------------------------------------------------------------
-// Gang solve: `nwg` workgroups (ranks 0..nwg-1) each own a column slice of S
-// columns and meet at one barrier per round.  Used by the whole-GPU kernel
-// (the gang is the grid) and by the serving kernel (a gang per large query).
-// ---------------------------------------------------------------------------
-
-// Barrier number b (1, 2, ...) of a gang of `members` workgroups: arrivals are
-// counted in bw->bar, and the member whose arrival completes b * members
-// publishes b in bw->gen, which the others poll.  Every wave first waits until
-// its own stores have left the CU (s_waitcnt 0), so after the workgroup barrier
-// they all sit in this XCD's L2; one agent-scope release by thread 0 then writes
-// that L2 back before the arrival, and one agent-scope acquire after the wait
-// invalidates the CU's and XCD's caches, so records that other members
-// published (from any XCD) are read fresh.  One cache writeback and one
-// invalidate per workgroup, not per wave.  Gives up after `timeout` wall-clock
-// ticks (returns false) so that a gang that is not co-resident cannot hang.
-template <int T>
-__device__ __forceinline__ bool gang_barrier(Bar* bw, uint32_t b, uint32_t members, long long timeout,
-                                             SharedSolve<T>& sh) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t ok = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t old = __hip_atomic_fetch_add(&bw->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b * members - 1) {
-            // last arrival: every other member's records were written back before
-            // its increment, which this increment observed; release barrier b
-            __hip_atomic_store(&bw->gen, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&bw->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > timeout) {
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        sh.flag = ok;
-    }
-    __syncthreads();
-    return sh.flag != 0;
-}
-
-// Thread 0 of each member calls this once when it is done with the gang's
-// words; the last of `members` resets them for the next use.  Returns true in
-// the last member.
-__device__ __forceinline__ bool gang_leave(Bar* bw, uint32_t members) {
-    const uint32_t prev = __hip_atomic_fetch_add(&bw->exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev != members - 1) return false;
-    __hip_atomic_store(&bw->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&bw->gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&bw->exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
-}
-
-// The last workgroup of a launch publishes the launch's statistics and resets
-// the barrier words, the ticket counter and the accumulators for the next launch.
-__device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bool add_stats) {
-    if (threadIdx.x != 0) return;
-    if (st.status) __hip_atomic_fetch_or(&ctl->status_acc, st.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (add_stats) {
-        __hip_atomic_fetch_add(&ctl->acc[kStatRounds], st.rounds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&ctl->acc[kStatSettled], st.settled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&ctl->acc[kStatFallbacks], st.fallbacks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&ctl->acc[kStatBarriers], st.barriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const uint32_t prev = __hip_atomic_fetch_add(&ctl->b.exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gridDim.x - 1) {
-        for (int i = 0; i < kStatCount; ++i) {
-            ctl->last[i] = __hip_atomic_load(&ctl->acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        ctl->status = __hip_atomic_exchange(&ctl->status_acc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->next_item, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->b.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->b.gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctl->b.exit, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Publish this workgroup's record for the next round: the lowest (dist, vertex)
-// key among `cand` (one would-be dist per owned column, 0xffffffff = excluded),
-// the vertices of the slice at that dist, and the zero-weight hazard flag.
-template <int T, int G>
-__device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layout& lo, int64_t col0,
-                                        uint32_t zero, Pub* __restrict__ pub, int32_t* __restrict__ list,
-                                        SharedSolve<T>& sh) {
-    uint64_t key = kNoKey;
-    if (lo.r == 0) {
-#pragma unroll
-        for (int k = 0; k < G; ++k)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (cand[k][j] != 0xffffffffu)
-                    key = umin64(key, make_key(cand[k][j], (uint32_t)(col0 + local_col(lo, k, j))));
-    }
-    block_min_or<T>(key, zero, sh.red);
-    const uint32_t dmin = (uint32_t)(key >> 32);
-    uint32_t mask = 0;
-    if (lo.r == 0 && key != kNoKey && dmin < kInf) {
-#pragma unroll
-        for (int k = 0; k < G; ++k)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (cand[k][j] == dmin) mask |= 1u << (4 * k + j);
-    }
-    uint32_t total;
-    uint32_t rank = block_excl_scan<T>(__popc(mask), total, sh.red);
-#pragma unroll
-    for (int k = 0; k < G; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (mask >> (4 * k + j) & 1u) list[rank++] = (int32_t)(col0 + local_col(lo, k, j));
-    if (threadIdx.x == 0) {
-        pub->key = key;
-        pub->count = total;
-        pub->flags = zero;
-    }
-}
-
-// Entry e0 + threadIdx.x of the round's bucket, i.e. of the concatenation (in
-// workgroup order) of the lists of the records whose minimum equals d.
-// sh.pre / sh.cnt hold each record's prefix offset and count.
-template <int T>
-__device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const int32_t* __restrict__ rl,
-                                                int nwg, int S, uint32_t e0, uint32_t M) {
-    const uint32_t e = e0 + threadIdx.x;
-    if (e >= M) return 0;
-    int lo_i = 0, hi_i = nwg - 1;  // last record whose prefix is <= e (its count is non-zero)
-    while (lo_i < hi_i) {
-        const int mid = (lo_i + hi_i + 1) >> 1;
-        if (sh.pre[mid] <= e) lo_i = mid;
-        else hi_i = mid - 1;
-    }
-    return rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
-}
-
-// Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
-// entries (double-buffered by barrier parity).  Returns false if a barrier
-// wait timed out.  `trace` (may be null) receives rank 0's round trace.
-template <int T, int G, int U, typename E, bool NT = false>
-__device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
-                           int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
-                           int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
-                           int32_t* __restrict__ lists, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
-    static_assert(T == kCap, "one staged bucket entry per thread");
-    const int64_t col0 = (int64_t)g * S;
-    const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
-    const Layout lo = make_layout<T>(S);
-    Cols<G> cs;
-    init_cols(cs, lo, col0, width, src, pred);
-
-    // initial record: the committed state (dist[src] = 0)
-    uint32_t cand[G][4];
-#pragma unroll
-    for (int k = 0; k < G; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
-    uint32_t b = 0;  // barriers passed
-    publish<T, G>(cand, lo, col0, 0u, &pubs[g], &lists[(int64_t)g * S], sh);
-    bool ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
-
-    bool pending = false;
-    uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
-    while (ok) {
-        const int slot = (b - 1) & 1;
-        const Pub* rp = pubs + (size_t)slot * nwg;
-        const int32_t* rl = lists + (size_t)slot * nwg * S;
-        Pub rec = {kNoKey, 0, 0};
-        if ((int)threadIdx.x < nwg) rec = rp[threadIdx.x];
-        uint64_t K = rec.key;
-        uint32_t Z = rec.flags;
-        block_min_or<T>(K, Z, sh.red);
-        if (pending) {
-            pending = false;
-            if (Z) {
-                // a fused round read a zero-weight edge out of its bucket: discard it
-                // and settle only the bucket's lowest-index vertex (one literal step)
-                ++st.fallbacks;
-                st.status |= kStatusZeroFallback;
-                reset_best(cs);
-                if (threadIdx.x == 0) sh.list[0] = (int32_t)pu0;
-                __syncthreads();
-                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
-                merge_partitions<T, G>(cs, lo, sh.mrg);
-                if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, owner_bit(lo, (int64_t)pu0 - col0, width), pred);
-                else reset_best(cs);
-                st.settled += 1;
-#pragma unroll
-                for (int k = 0; k < G; ++k)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
-                const int ns = b & 1;
-                publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
-                              &lists[((size_t)ns * nwg + g) * S], sh);
-                ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
-                continue;
-            }
-            if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
-            else reset_best(cs);
-            st.settled += pM;
-        }
-        const uint32_t d = (uint32_t)(K >> 32);
-        if (K == kNoKey || d >= kInf) break;
-        const uint32_t u0 = (uint32_t)K;
-        ++st.rounds;
-        const long long t_round = wall_clock64();
-
-        // the round's bucket: records whose local minimum equals d
-        uint32_t M;
-        uint32_t bucket;
-        if (literal) {
-            M = 1;
-            bucket = owner_bit(lo, (int64_t)u0 - col0, width);
-            if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
-            __syncthreads();
-            stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
-        } else {
-            bucket = bucket_mask(cs, d);
-            const uint32_t c = ((int)threadIdx.x < nwg && (uint32_t)(rec.key >> 32) == d) ? rec.count : 0u;
-            const uint32_t pre = block_excl_scan<T>(c, M, sh.red);
-            if ((int)threadIdx.x < nwg) {
-                sh.pre[threadIdx.x] = pre;
-                sh.cnt[threadIdx.x] = c;
-            }
-            __syncthreads();
-            // stage the bucket chunk by chunk; the next chunk's entries are loaded
-            // while the current chunk's rows stream
-            int32_t nxt = gather_entry<T>(sh, rl, nwg, S, 0, M);
-            for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
-                sh.list[threadIdx.x] = nxt;
-                __syncthreads();
-                if (e0 + kCap < M) nxt = gather_entry<T>(sh, rl, nwg, S, e0 + kCap, M);
-                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
-                __syncthreads();
-            }
-        }
-        merge_partitions<T, G>(cs, lo, sh.mrg);
-        if (trace && g == 0 && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
-            trace->trace_t[st.rounds - 1] = t_round;
-            trace->trace_m[st.rounds - 1] = M;
-        }
-
-        // would-be state if this round is applied; publish it with the hazard flag
-        uint32_t neg = 0;
-#pragma unroll
-        for (int k = 0; k < G; ++k)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cand[k][j] = would_be(cs, k, j, d, bucket, neg);
-        st.status |= neg;
-        const uint32_t zero = (!literal && lo.r == 0) ? zero_hazard(cs, d) : 0u;
-        const int ns = b & 1;
-        publish<T, G>(cand, lo, col0, zero, &pubs[(size_t)ns * nwg + g], &lists[((size_t)ns * nwg + g) * S], sh);
-        pending = true;
-        pd = d;
-        pu0 = u0;
-        pbucket = bucket;
-        pM = M;
-        ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
-    }
-    if (!ok) st.status |= kStatusTimeout;
-    write_dist(cs, lo, col0, width, dist);
-    st.barriers += b;
-    if (trace && g == 0 && threadIdx.x == 0) {
-        const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
-        trace->trace_t[nr] = wall_clock64();
-        trace->trace_n = (uint32_t)nr;
-    }
-    uint32_t s = st.status;
-    uint64_t dummy = kNoKey;
-    block_min_or<T>(dummy, s, sh.red);
-    st.status = s;
-    return ok;
 }
 
 template <int T, int G, int U>

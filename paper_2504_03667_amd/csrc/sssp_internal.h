@@ -37,6 +37,12 @@ hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pu
 int max_grid_slice();
 int grid_occupancy(int slice, int* per_cu);
 
+// Label-correcting solve on a cooperative grid of nwg workgroups (slices of S
+// columns); lists: 2 * nwg * S 64-bit entries.
+hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, uint64_t* lists,
+                     bool plain, hipStream_t s);
+int lc_occupancy(int slice, int* per_cu);
+
 // One instance of a batched launch or one served query, as the kernels read it.
 struct BatchItem {
     const void* W;       // int32_t, uint16_t or uint8_t entries (elem bytes each)

@@ -30,6 +30,7 @@ SSSP_FLAG_LITERAL = 1
 SSSP_FLAG_SINGLE = 2
 SSSP_FLAG_GRID = 4
 SSSP_FLAG_COMPACT = 8
+SSSP_FLAG_LABEL_CORRECTING = 16
 
 SSSP_STAT_ROUNDS, SSSP_STAT_SETTLED, SSSP_STAT_FALLBACKS, SSSP_STAT_BARRIERS = range(4)
 
@@ -178,8 +179,10 @@ def sssp_dense_solve(W, n, src, dist, pred, stream=None):
 
 def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroups=0, stream=None):
     """sssp_dense_solve_ex: W is an int32 device tensor holding n rows of stride ld."""
-    if W.numel() < (n - 1) * ld + n:
-        raise ValueError("W is too small for n rows of stride ld")
+    # W may be a row-strided view (e.g. big[:, :n]): check the storage behind it
+    avail = W.untyped_storage().nbytes() // 4 - W.storage_offset()
+    if n < 1 or avail < (n - 1) * ld + n or (W.dim() == 2 and W.stride(1) != 1):
+        raise ValueError("W is too small for n rows of stride ld, or its rows are not contiguous")
     return _check(lib().sssp_dense_solve_ex(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
                                             _ptr(pred, "pred"), flags,
                                             _tuning(threads, workgroups), _stream(stream)))
@@ -229,6 +232,10 @@ def sssp_dense_solve_batched(items, flags=0, threads=0, workgroups=0, stream=Non
 
 def sssp_batch_max_n():
     return lib().sssp_batch_max_n()
+
+
+def sssp_single_max_n():
+    return lib().sssp_single_max_n()
 
 
 def sssp_dense_validate(W, ld, n, stream=None):
