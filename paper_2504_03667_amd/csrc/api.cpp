@@ -114,6 +114,9 @@ int ensure(Scratch* sc, X*& p, size_t& cap, size_t need, const char* what) {
     hipError_t e = hipMalloc(&p, n * sizeof(X));
     if (e != hipSuccess) return fail(SSSP_ENOMEM, "hipMalloc(%s, %zu bytes): %s", what, n * sizeof(X),
                                      hipGetErrorString(e));
+    // exchange records must start without stamps (see gang_exchange)
+    e = hipMemset(p, 0, n * sizeof(X));
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(scratch)");
     cap = n;
     return SSSP_OK;
 }
@@ -144,7 +147,7 @@ int single_crossover() {
         int v = atoi(s);
         if (v > 0) return v;
     }
-    return 2048;
+    return 1024;
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -186,9 +189,9 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         if (e != hipSuccess) return hip_fail(e, "launch(one-workgroup solve)");
     } else {
         int per_cu = 0;
-        // slice width: about 128 columns (512 B of each row) per workgroup by default, as
+        // slice width: about 64 columns (256 B of each row) per workgroup by default, as
         // many workgroups as fit; wider slices when n outgrows the grid
-        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 127) / 128);
+        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 63) / 64);
         if (lc && (flags & SSSP_FLAG_SINGLE)) want = 1;
         int S = (int)(((int64_t)n + want - 1) / want);
         S = (S + 3) & ~3;

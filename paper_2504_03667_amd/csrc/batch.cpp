@@ -201,6 +201,8 @@ struct sssp_batch_plan {
         if (e == hipSuccess)
             e = hipMemcpy(d_parts, b.parts.data(), sizeof(BatchPart) * b.parts.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(d_bars, 0, sizeof(Bar) * b.items.size());
+        // exchange records must start without stamps (see gang_exchange)
+        if (e == hipSuccess && b.arena_bytes) e = hipMemset(d_arena, 0, b.arena_bytes);
         if (e != hipSuccess) return hip_err(e, "uploading a batch plan");
         nparts = (int32_t)b.parts.size();
         info.max_parts = b.max_parts;
@@ -272,7 +274,10 @@ int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t 
     e = hipMemcpyAsync(d_items, b.items.data(), sizeof(BatchItem) * b.items.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_parts, b.parts.data(), sizeof(BatchPart) * b.parts.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(d_bars, 0, sizeof(Bar) * b.items.size(), s);
+    // barrier words and exchange records start zeroed (fill kernels, not memset
+    // nodes, so that the call can be captured into a graph)
+    if (e == hipSuccess) e = zero_fill(d_bars, sizeof(Bar) * b.items.size(), s);
+    if (e == hipSuccess && b.arena_bytes) e = zero_fill(d_arena, b.arena_bytes, s);
     if (e == hipSuccess)
         e = launch_batch(d_items, d_parts, (int32_t)b.parts.size(), d_bars, d_arena, flags & SSSP_FLAG_LITERAL,
                          khz * 10000, ctl, nwg, s);

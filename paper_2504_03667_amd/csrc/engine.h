@@ -66,7 +66,7 @@ struct Ctl {
     uint32_t status_acc;  // status bits OR-ed during the current launch
     uint32_t status;      // status of the last finished launch
     uint32_t trace_n;     // rounds recorded in trace_t / trace_m by the last launch
-    uint32_t pad;
+    uint32_t epoch;       // launches finished; stamps the exchange records of the next one
     unsigned long long acc[kStatCount];
     unsigned long long last[kStatCount];
     unsigned long long next_item;  // work-queue ticket counter (batched kernels)
@@ -74,12 +74,26 @@ struct Ctl {
     uint32_t trace_m[kTraceCap];       // rows streamed in each round
 };
 
-// One workgroup's contribution to a round, published before a grid barrier.
-struct Pub {
+// One workgroup's contribution to a round.  Written and read only with
+// agent-scope atomic accesses, which are coherent across XCDs without cache
+// writebacks or invalidates; `stamp` is stored last and tells the readers that
+// the rest (and the workgroup's list entries) is in place.
+struct alignas(32) Pub {
+    uint64_t stamp;  // (epoch << 32) | barrier number of the exchange it belongs to
     uint64_t key;    // (would-be local min dist << 32) | lowest vertex at that dist; kNoKey if none
     uint32_t count;  // vertices of the slice at that dist, listed in the slot's list region
     uint32_t flags;  // bit 0: a zero-weight edge from the bucket to an unvisited vertex was seen
+    uint64_t pad;
 };
+
+template <typename X>
+__device__ __forceinline__ X ld_agent(const X* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename X>
+__device__ __forceinline__ void st_agent(X* p, X v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return b < a ? b : a; }
 __device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
@@ -322,21 +336,66 @@ __device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const
     }
 }
 
-// Merge the P partitions' minima into the owner threads (partition 0).
-// Only used when P > 1, which implies G == 1.  `mrg` holds T * 4 keys.
+// Merge the P partitions' minima into the owner threads (partition 0): every
+// partition takes an LDS atomic minimum into one key per column, then the
+// owners read the result and put the all-ones key back.  `mrg` (4 * L keys or
+// more) is all ones between merges (clear_merge at the start of a solve).
+// Only used when P > 1, which implies G == 1.
 template <int T, int G>
 __device__ __forceinline__ void merge_partitions(Cols<G>& cs, const Layout& lo, uint64_t* mrg) {
     if (lo.P == 1) return;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) mrg[(size_t)j * T + threadIdx.x] = cs.best[0][j];
+    for (int j = 0; j < 4; ++j)
+        if (cs.best[0][j] != kNoKey)
+            __hip_atomic_fetch_min(&mrg[j * lo.L + lo.c], cs.best[0][j], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
     if (lo.r == 0) {
-        for (int p = 1; p < lo.P; ++p)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                cs.best[0][j] = umin64(cs.best[0][j], mrg[(size_t)j * T + p * lo.L + lo.c]);
+        for (int j = 0; j < 4; ++j) {
+            cs.best[0][j] = mrg[j * lo.L + lo.c];
+            mrg[j * lo.L + lo.c] = kNoKey;
+        }
     }
-    __syncthreads();
+}
+
+// Fill the partition-merge area (n64 keys) with all ones; ordered before its
+// first use by the workgroup barriers that precede any merge.
+template <int T>
+__device__ __forceinline__ void clear_merge(uint64_t* mrg, int n64) {
+    for (int i = threadIdx.x; i < n64; i += T) mrg[i] = kNoKey;
+}
+
+// Minimum of key and OR of flags over the slice owners (the first L threads,
+// partition 0); valid in the owners.  Threads that are not owners must pass
+// kNoKey / 0.  When the owners fit in wave 0 this is a wave reduction with no
+// workgroup barrier (and only wave 0 takes part); otherwise a block reduction
+// that every thread must enter.
+template <int T>
+__device__ __forceinline__ void owner_min_or(uint64_t& key, uint32_t& flags, int L, Red<T>& red) {
+    if (L <= kWave) {
+        if (threadIdx.x < kWave) {
+            key = wave_min64(key);
+            flags = wave_or32(flags);
+        }
+        return;
+    }
+    block_min_or<T>(key, flags, red);
+}
+
+// Exclusive prefix sum over the owners (same rules as owner_min_or); `total`
+// gets the sum.
+template <int T>
+__device__ __forceinline__ uint32_t owner_excl_scan(uint32_t x, uint32_t& total, int L, Red<T>& red) {
+    if (L <= kWave) {
+        uint32_t inc = 0;
+        if (threadIdx.x < kWave) {
+            inc = wave_scan32(x);
+            total = __shfl(inc, kWave - 1, kWave);
+        }
+        return inc - x;
+    }
+    return block_excl_scan<T>(x, total, red);
 }
 
 template <int G>

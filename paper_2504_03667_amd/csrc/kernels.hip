@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "engine.h"
 #include "solve.h"
 #include "sssp_internal.h"
@@ -58,8 +60,9 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
                                             Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
+    const uint32_t epoch = ld_agent(&ctl->epoch);
     solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
-                        blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl);
+                        blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl, epoch);
     finish_launch(ctl, st, blockIdx.x == 0);
 }
 
@@ -83,12 +86,12 @@ __device__ __attribute__((noinline)) SolveStats single_variant(BatchItem I, bool
 
 template <int T, int G, typename E>
 __device__ __attribute__((noinline)) SolveStats gang_variant(BatchItem I, int part, bool literal, long long timeout,
-                                                             Bar* bw, char* arena) {
+                                                             Bar* bw, char* arena, uint32_t epoch) {
     SolveStats st = {0, 0, 0, 0, 0};
     Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
     int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * I.parts);
     solve_gang<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, literal, I.S,
-                           part, I.parts, timeout, bw, pubs, lists, g_sh<T>, st, nullptr);
+                           part, I.parts, timeout, bw, pubs, lists, g_sh<T>, st, nullptr, epoch);
     if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
     return st;
 }
@@ -103,24 +106,25 @@ __device__ __forceinline__ SolveStats single_by_size(const BatchItem& I, bool li
 
 template <int T, typename E>
 __device__ __forceinline__ SolveStats gang_by_size(const BatchItem& I, int part, bool literal, long long timeout,
-                                                   Bar* bw, char* arena) {
+                                                   Bar* bw, char* arena, uint32_t epoch) {
     const int groups = (I.S + 3) / 4;
-    if (groups <= T) return gang_variant<T, 1, E>(I, part, literal, timeout, bw, arena);
-    if (groups <= 2 * T) return gang_variant<T, 2, E>(I, part, literal, timeout, bw, arena);
-    return gang_variant<T, 4, E>(I, part, literal, timeout, bw, arena);
+    if (groups <= T) return gang_variant<T, 1, E>(I, part, literal, timeout, bw, arena, epoch);
+    if (groups <= 2 * T) return gang_variant<T, 2, E>(I, part, literal, timeout, bw, arena, epoch);
+    return gang_variant<T, 4, E>(I, part, literal, timeout, bw, arena, epoch);
 }
 
 template <int T>
+// epoch: unique to this use of the item's exchange records (see gang_exchange).
 __device__ __forceinline__ SolveStats solve_item(const BatchItem& I, int part, bool literal, long long timeout,
-                                                 Bar* bw, char* arena) {
+                                                 Bar* bw, char* arena, uint32_t epoch) {
     if (I.parts <= 1) {
         if (I.elem == 1) return single_by_size<T, uint8_t>(I, literal);
         if (I.elem == 2) return single_by_size<T, uint16_t>(I, literal);
         return single_by_size<T, int32_t>(I, literal);
     }
-    if (I.elem == 1) return gang_by_size<T, uint8_t>(I, part, literal, timeout, bw, arena);
-    if (I.elem == 2) return gang_by_size<T, uint16_t>(I, part, literal, timeout, bw, arena);
-    return gang_by_size<T, int32_t>(I, part, literal, timeout, bw, arena);
+    if (I.elem == 1) return gang_by_size<T, uint8_t>(I, part, literal, timeout, bw, arena, epoch);
+    if (I.elem == 2) return gang_by_size<T, uint16_t>(I, part, literal, timeout, bw, arena, epoch);
+    return gang_by_size<T, int32_t>(I, part, literal, timeout, bw, arena, epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -135,6 +139,7 @@ __global__ __launch_bounds__(T) void k_batch(const BatchItem* __restrict__ items
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats total = {0, 0, 0, 0, 0};
     const bool literal = (flags & kFlagLiteral) != 0;
+    const uint32_t epoch = ld_agent(&ctl->epoch);
     for (;;) {
         if (threadIdx.x == 0)
             sh.item = (int32_t)__hip_atomic_fetch_add(&ctl->next_item, 1ull, __ATOMIC_RELAXED,
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(T) void k_batch(const BatchItem* __restrict__ items
         if (t >= nparts) break;
         const BatchPart pt = parts[t];
         const BatchItem I = items[pt.item];
-        const SolveStats st = solve_item<T>(I, pt.part, literal, timeout, bars ? &bars[pt.item] : nullptr, arena);
+        const SolveStats st = solve_item<T>(I, pt.part, literal, timeout, bars ? &bars[pt.item] : nullptr, arena, epoch);
         total.status |= st.status;
         if (pt.part == 0) {  // every gang member computes the same counts; count them once
             total.rounds += st.rounds;
@@ -183,6 +188,13 @@ __global__ void k_weight_range(const int32_t* __restrict__ W, int64_t ld, int32_
         atomicMin(&out[0], smin[0]);
         atomicMax(&out[1], smax[0]);
     }
+}
+
+// Clears `words` 32-bit words (scratch that a launch expects zeroed; a kernel
+// rather than a memset node, so that the call can be captured into a graph).
+__global__ void k_zero(uint32_t* __restrict__ p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // Exact compact copy: INT32_MAX -> the all-ones code of E, other entries as is
@@ -255,14 +267,15 @@ __device__ __forceinline__ bool serve_claim(const ServeArgs& a, ServeDesc* out) 
 
 template <int T>
 __global__ __launch_bounds__(T) void k_serve(ServeArgs a) {
-    SharedSolve<T>& sh = g_sh<T>;
     __shared__ ServeDesc q;
     __shared__ int32_t leave;
     for (;;) {
         if (threadIdx.x == 0) leave = serve_claim(a, &q) ? 1 : 0;
         __syncthreads();
         if (leave) break;
-        const SolveStats st = solve_item<T>(q.item, q.part, false, a.timeout, &a.bars[q.qslot], a.arena);
+        // a query's ticket is unique to it: the epoch of its gang's records
+        const SolveStats st = solve_item<T>(q.item, q.part, false, a.timeout, &a.bars[q.qslot], a.arena,
+                                            (uint32_t)q.ticket);
         // completion: the last part to finish writes the slot's record to host memory
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -379,6 +392,15 @@ hipError_t compact_copy(const int32_t* W, int64_t ld, int32_t n, void* C, int64_
         hipLaunchKernelGGL((k_compact<uint16_t>), grid, dim3(256), 0, s, W, ld, n, static_cast<uint16_t*>(C), ldc);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t s) {
+    if (bytes % 4) return hipErrorInvalidValue;
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t*>(p), words);
     return hipGetLastError();
 }
 

@@ -161,33 +161,42 @@ __device__ __forceinline__ void lc_pred_rows(uint64_t (&key)[G][4], const uint32
     }
 }
 
-// Merge the P row partitions' results into the owners (partition 0); P > 1
-// implies G == 1.  Minimum of 32-bit values / of 64-bit keys.
+// Merge the P row partitions' results into the owners (partition 0) with LDS
+// atomic minima, as merge_partitions does (P > 1 implies G == 1; the merge area
+// is all ones between merges: the 32-bit view of the all-ones 64-bit key).
 template <int T, int G>
 __device__ __forceinline__ void lc_merge32(uint32_t (&best)[G][4], const Layout& lo, uint64_t* mrg) {
     if (lo.P == 1) return;
     uint32_t* m32 = reinterpret_cast<uint32_t*>(mrg);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) m32[(size_t)j * T + threadIdx.x] = best[0][j];
+    for (int j = 0; j < 4; ++j)
+        if (best[0][j] != 0xffffffffu)
+            __hip_atomic_fetch_min(&m32[j * lo.L + lo.c], best[0][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
-    if (lo.r == 0)
-        for (int p = 1; p < lo.P; ++p)
+    if (lo.r == 0) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) best[0][j] = min(best[0][j], m32[(size_t)j * T + p * lo.L + lo.c]);
-    __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            best[0][j] = m32[j * lo.L + lo.c];
+            m32[j * lo.L + lo.c] = 0xffffffffu;
+        }
+    }
 }
 
 template <int T, int G>
 __device__ __forceinline__ void lc_merge64(uint64_t (&key)[G][4], const Layout& lo, uint64_t* mrg) {
     if (lo.P == 1) return;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) mrg[(size_t)j * T + threadIdx.x] = key[0][j];
+    for (int j = 0; j < 4; ++j)
+        if (key[0][j] != kNoKey)
+            __hip_atomic_fetch_min(&mrg[j * lo.L + lo.c], key[0][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
-    if (lo.r == 0)
-        for (int p = 1; p < lo.P; ++p)
+    if (lo.r == 0) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) key[0][j] = umin64(key[0][j], mrg[(size_t)j * T + p * lo.L + lo.c]);
-    __syncthreads();
+        for (int j = 0; j < 4; ++j) {
+            key[0][j] = mrg[j * lo.L + lo.c];
+            mrg[j * lo.L + lo.c] = kNoKey;
+        }
+    }
 }
 
 // Publish the owned columns selected by `mask` as (dist, vertex) entries of
@@ -196,28 +205,65 @@ template <int T, int G>
 __device__ __forceinline__ void lc_publish(uint32_t mask, const uint32_t (&dv)[G][4], const Layout& lo, int64_t col0,
                                            uint32_t flags, Pub* __restrict__ pub, uint64_t* __restrict__ list,
                                            SharedSolve<T>& sh) {
-    uint32_t total;
-    uint32_t rank = block_excl_scan<T>(__popc(mask), total, sh.red);
+    uint32_t total = 0;
+    uint32_t rank = owner_excl_scan<T>(__popc(mask), total, lo.L, sh.red);
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (mask >> (4 * k + j) & 1u) list[rank++] = lc_entry(dv[k][j], (uint32_t)(col0 + local_col(lo, k, j)));
+            if (mask >> (4 * k + j) & 1u)
+                st_agent(&list[rank++], lc_entry(dv[k][j], (uint32_t)(col0 + local_col(lo, k, j))));
     if (threadIdx.x == 0) {
-        pub->key = total;
-        pub->count = total;
-        pub->flags = flags;
+        st_agent(&pub->key, (uint64_t)total);
+        st_agent(&pub->count, total);
+        st_agent(&pub->flags, flags);
     }
 }
 
-// Read the records of the last barrier: per-record prefix offsets and counts
-// into sh.pre / sh.cnt; returns the total, ORs the records' flags into *flags.
+// Read the records of the last exchange: per-record prefix offsets and counts
+// into sh.pre / sh.cnt; returns the total and ORs the records' flags into
+// *flags.  Wave 0 does it for gangs of up to 256 members (one workgroup
+// barrier), as read_records does.
 template <int T>
 __device__ __forceinline__ uint32_t lc_records(const Pub* rp, int nwg, SharedSolve<T>& sh, uint32_t& flags) {
+    if (nwg <= 4 * kWave) {
+        if (threadIdx.x < kWave) {
+            const int q = (nwg + kWave - 1) / kWave;
+            const int i0 = (int)threadIdx.x * q;
+            uint32_t cnt[4];
+            uint32_t f = 0, local = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                cnt[k] = 0;
+                if (k < q && i0 + k < nwg) {
+                    cnt[k] = ld_agent(&rp[i0 + k].count);
+                    f |= ld_agent(&rp[i0 + k].flags);
+                }
+                local += cnt[k];
+            }
+            f = wave_or32(f);
+            const uint32_t inc = wave_scan32(local);
+            uint32_t run = inc - local;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < q && i0 + k < nwg) {
+                    sh.pre[i0 + k] = run;
+                    sh.cnt[i0 + k] = cnt[k];
+                    run += cnt[k];
+                }
+            if (threadIdx.x == kWave - 1) {
+                sh.rz = f;
+                sh.rm = inc;
+            }
+        }
+        __syncthreads();
+        flags = sh.rz;
+        return sh.rm;
+    }
     uint32_t c = 0, f = 0;
     if ((int)threadIdx.x < nwg) {
-        c = rp[threadIdx.x].count;
-        f = rp[threadIdx.x].flags;
+        c = ld_agent(&rp[threadIdx.x].count);
+        f = ld_agent(&rp[threadIdx.x].flags);
     }
     uint32_t M;
     const uint32_t pre = block_excl_scan<T>(c, M, sh.red);
@@ -243,7 +289,7 @@ __device__ __forceinline__ uint64_t lc_gather(const SharedSolve<T>& sh, const ui
         if (sh.pre[mid] <= e) lo_i = mid;
         else hi_i = mid - 1;
     }
-    return rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
+    return ld_agent(&rl[(size_t)lo_i * S + (e - sh.pre[lo_i])]);
 }
 
 // Stage the M listed rows chunk by chunk into LDS and run `pass` over each
@@ -265,14 +311,15 @@ __device__ __forceinline__ void lc_stream(const uint64_t* rl, int nwg, int S, ui
 enum LcResult { kLcDone = 0, kLcTimeout = 1, kLcFallback = 2 };
 
 // Rank g of a gang of nwg workgroups (the whole grid).  pubs: 2 * nwg records;
-// lists: 2 * nwg * S 64-bit entries, double-buffered by barrier parity.  *b
-// counts the barriers passed (a fallback solve continues the numbering).
+// lists: 2 * nwg * S 64-bit entries, double-buffered by exchange parity.  b
+// counts the exchanges passed (a fallback solve continues the numbering);
+// epoch stamps this launch's records (see gang_exchange).
 template <int T, int G, int U, typename E, bool NT>
 __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                                         int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, int S,
                                         int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
                                         uint64_t* __restrict__ lists, SharedSolve<T>& sh, SharedLC<T>& lc,
-                                        SolveStats& st, uint32_t& b, Ctl* trace) {
+                                        SolveStats& st, uint32_t& b, uint32_t epoch, Ctl* trace) {
     static_assert(T == kCap, "one staged entry per thread");
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
@@ -290,12 +337,19 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
             own |= mine ? 1u << (4 * k + j) : 0u;
             chg |= is_src ? 1u << (4 * k + j) : 0u;
         }
+    clear_merge<T>(sh.mrg, 4 * T);
     auto slot_pub = [&](uint32_t s) { return pubs + (size_t)s * nwg; };
     auto slot_list = [&](uint32_t s) { return lists + (size_t)s * nwg * S; };
+    const uint64_t ep = (uint64_t)epoch << 32;
+    // the next exchange: members' records of slot (b & 1) carry stamp b + 1
+    auto exchange = [&]() {
+        ++b;
+        return gang_exchange<T>(slot_pub((b - 1) & 1), g, ep | b, (uint32_t)nwg, timeout);
+    };
 
     // sweep 1 relaxes the source's row
     lc_publish<T, G>(chg, dv, lo, col0, 0u, &slot_pub(b & 1)[g], slot_list(b & 1) + (size_t)g * S, sh);
-    bool ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
+    bool ok = exchange();
     uint32_t neg = 0;
     while (ok) {
         const uint32_t s = (b - 1) & 1;
@@ -330,7 +384,7 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
                     }
         }
         lc_publish<T, G>(chg, dv, lo, col0, 0u, &slot_pub(b & 1)[g], slot_list(b & 1) + (size_t)g * S, sh);
-        ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
+        ok = exchange();
     }
     st.status |= neg;
     if (!ok) return kLcTimeout;
@@ -343,7 +397,7 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
         for (int j = 0; j < 4; ++j)
             if ((own >> (4 * k + j) & 1u) && dv[k][j] < kInf) reach |= 1u << (4 * k + j);
     lc_publish<T, G>(reach, dv, lo, col0, 0u, &slot_pub(b & 1)[g], slot_list(b & 1) + (size_t)g * S, sh);
-    if (!gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh)) return kLcTimeout;
+    if (!exchange()) return kLcTimeout;
     uint32_t f;
     const uint32_t R = lc_records<T>(slot_pub((b - 1) & 1), nwg, sh, f);
     st.settled += R;
@@ -383,11 +437,11 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
     block_min_or<T>(dummy, zero, sh.red);
     if (threadIdx.x == 0) {
         Pub* p = &slot_pub(b & 1)[g];
-        p->key = 0;
-        p->count = 0;
-        p->flags = zero;
+        st_agent(&p->key, (uint64_t)0);
+        st_agent(&p->count, 0u);
+        st_agent(&p->flags, zero);
     }
-    if (!gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh)) return kLcTimeout;
+    if (!exchange()) return kLcTimeout;
     uint32_t Z;
     (void)lc_records<T>(slot_pub((b - 1) & 1), nwg, sh, Z);
     if (Z) return kLcFallback;
@@ -414,8 +468,9 @@ __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t
     SolveStats st = {0, 0, 0, 0, 0};
     uint32_t b = 0;
     const bool vec = (flags & kFlagVec) != 0;
+    const uint32_t epoch = ld_agent(&ctl->epoch);
     const int r = solve_lc<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, vec, S, blockIdx.x, gridDim.x, timeout,
-                                                   &ctl->b, pubs, lists, sh, g_lc<T>, st, b, ctl);
+                                                   &ctl->b, pubs, lists, sh, g_lc<T>, st, b, epoch, ctl);
     if (r == kLcTimeout) {
         st.status |= kStatusTimeout;
         st.barriers += b;
@@ -425,7 +480,7 @@ __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t
         ++st.fallbacks;
         st.status |= kStatusZeroFallback;
         solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, vec, false, S, blockIdx.x, gridDim.x, timeout,
-                                           &ctl->b, pubs, reinterpret_cast<int32_t*>(lists), sh, st, ctl, b);
+                                           &ctl->b, pubs, reinterpret_cast<int32_t*>(lists), sh, st, ctl, epoch, b);
     } else {
         st.barriers += b;
     }

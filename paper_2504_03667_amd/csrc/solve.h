@@ -19,6 +19,8 @@ struct SharedSolve {
     uint64_t mrg[4 * T];
     uint32_t pre[T];
     uint32_t cnt[T];
+    uint64_t rk;  // read_records results for the whole workgroup
+    uint32_t rz, rm;
     int32_t item;
     uint32_t flag;
 };
@@ -52,6 +54,7 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
     const Layout lo = make_layout<T>(n);
     Cols<G> cs;
     init_cols(cs, lo, 0, n, src, pred);
+    clear_merge<T>(sh.mrg, 4 * T);
     for (;;) {
         // a2/a3: argmin over unvisited vertices, lowest index on ties
         uint64_t key = local_argmin(cs, lo, 0);
@@ -129,45 +132,45 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
 // (the gang is the grid) and by the serving kernel (a gang per large query).
 // ---------------------------------------------------------------------------
 
-// Barrier number b (1, 2, ...) of a gang of `members` workgroups: arrivals are
-// counted in bw->bar, and the member whose arrival completes b * members
-// publishes b in bw->gen, which the others poll.  Every wave first waits until
-// its own stores have left the CU (s_waitcnt 0), so after the workgroup barrier
-// they all sit in this XCD's L2; one agent-scope release by thread 0 then writes
-// that L2 back before the arrival, and one agent-scope acquire after the wait
-// invalidates the CU's and XCD's caches, so records that other members
-// published (from any XCD) are read fresh.  One cache writeback and one
-// invalidate per workgroup, not per wave.  Gives up after `timeout` wall-clock
-// ticks (returns false) so that a gang that is not co-resident cannot hang.
+// Exchange number b of a gang of `members` workgroups, rank g: publishes this
+// member's record in `slot` (filled by publish()) and waits until every
+// member's record there carries the same stamp.  Records and list entries are
+// written and read with agent-scope atomic accesses (coherent across XCDs
+// without cache writebacks or invalidates), so the only ordering needed is that
+// a member's other stores are complete before its stamp: every wave waits for
+// its stores (s_waitcnt 0) before the workgroup barrier, and thread 0 stores the
+// stamp after it.  A reader reads a record's other fields only after seeing its
+// stamp.  Thread t < members polls record t; nothing is counted in a shared
+// word.  Gives up after `timeout` wall-clock ticks (returns false) so that a
+// gang that is not co-resident cannot hang.  stamp = (epoch << 32) | b with an
+// epoch unique to this use of the records' memory, so a record left from an
+// earlier use never matches.
 template <int T>
-__device__ __forceinline__ bool gang_barrier(Bar* bw, uint32_t b, uint32_t members, long long timeout,
-                                             SharedSolve<T>& sh) {
+__device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, uint32_t members, long long timeout) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (members == 1) return true;  // one workgroup: its own barrier orders everything
     if (threadIdx.x == 0) {
-        uint32_t ok = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t old = __hip_atomic_fetch_add(&bw->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b * members - 1) {
-            // last arrival: every other member's records were written back before
-            // its increment, which this increment observed; release barrier b
-            __hip_atomic_store(&bw->gen, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&bw->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > timeout) {
-                    ok = 0;
-                    break;
-                }
+        __builtin_amdgcn_s_waitcnt(0);
+        st_agent(&slot[g].stamp, stamp);
+    }
+    int late = 0;
+    if (threadIdx.x < members) {
+        // polls back off (up to ~1 us apart) so that members waiting through a
+        // long round do not load the memory system the others are streaming from
+        const long long t0 = wall_clock64();
+        unsigned naps = 1;
+        while (ld_agent(&slot[threadIdx.x].stamp) != stamp) {
+            for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
+            if (naps < 32) naps <<= 1;
+            if (wall_clock64() - t0 > timeout) {
+                late = 1;
+                break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        sh.flag = ok;
     }
-    __syncthreads();
-    return sh.flag != 0;
+    return __syncthreads_or(late) == 0;
 }
 
 // Thread 0 of each member calls this once when it is done with the gang's
@@ -200,6 +203,8 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
             __hip_atomic_store(&ctl->acc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         ctl->status = __hip_atomic_exchange(&ctl->status_acc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // a new epoch for the next launch's exchange records
+        __hip_atomic_fetch_add(&ctl->epoch, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->next_item, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->b.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctl->b.gen, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -223,7 +228,7 @@ __device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layo
                 if (cand[k][j] != 0xffffffffu)
                     key = umin64(key, make_key(cand[k][j], (uint32_t)(col0 + local_col(lo, k, j))));
     }
-    block_min_or<T>(key, zero, sh.red);
+    owner_min_or<T>(key, zero, lo.L, sh.red);
     const uint32_t dmin = (uint32_t)(key >> 32);
     uint32_t mask = 0;
     if (lo.r == 0 && key != kNoKey && dmin < kInf) {
@@ -233,18 +238,95 @@ __device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layo
             for (int j = 0; j < 4; ++j)
                 if (cand[k][j] == dmin) mask |= 1u << (4 * k + j);
     }
-    uint32_t total;
-    uint32_t rank = block_excl_scan<T>(__popc(mask), total, sh.red);
+    uint32_t total = 0;
+    uint32_t rank = owner_excl_scan<T>(__popc(mask), total, lo.L, sh.red);
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (mask >> (4 * k + j) & 1u) list[rank++] = (int32_t)(col0 + local_col(lo, k, j));
+            if (mask >> (4 * k + j) & 1u) st_agent(&list[rank++], (int32_t)(col0 + local_col(lo, k, j)));
     if (threadIdx.x == 0) {
-        pub->key = key;
-        pub->count = total;
-        pub->flags = zero;
+        st_agent(&pub->key, key);
+        st_agent(&pub->count, total);
+        st_agent(&pub->flags, zero);
     }
+}
+
+// After an exchange, the gang's nwg records of one slot: K = the lowest key,
+// Z = the OR of the flags; for the round's bucket (records whose key has dist
+// d = K >> 32) each record's count and offset go to sh.cnt / sh.pre and their
+// sum to M.  Wave 0 does it alone (up to 4 contiguous records per lane) and
+// shares the results through LDS after one workgroup barrier; gangs of more
+// than 256 members take a block-wide path.
+template <int T>
+__device__ __forceinline__ void read_records(const Pub* rp, int nwg, SharedSolve<T>& sh, uint64_t& K, uint32_t& Z,
+                                             uint32_t& M) {
+    if (nwg <= 4 * kWave) {
+        if (threadIdx.x < kWave) {
+            const int q = (nwg + kWave - 1) / kWave;
+            const int i0 = (int)threadIdx.x * q;
+            uint64_t key[4];
+            uint32_t cnt[4];
+            uint64_t kmin = kNoKey;
+            uint32_t f = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                key[k] = kNoKey;
+                cnt[k] = 0;
+                if (k < q && i0 + k < nwg) {
+                    key[k] = ld_agent(&rp[i0 + k].key);
+                    cnt[k] = ld_agent(&rp[i0 + k].count);
+                    f |= ld_agent(&rp[i0 + k].flags);
+                }
+                kmin = umin64(kmin, key[k]);
+            }
+            kmin = wave_min64(kmin);
+            f = wave_or32(f);
+            const uint32_t d = (uint32_t)(kmin >> 32);
+            uint32_t local = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (key[k] == kNoKey || (uint32_t)(key[k] >> 32) != d) cnt[k] = 0;
+                local += cnt[k];
+            }
+            const uint32_t inc = wave_scan32(local);
+            uint32_t run = inc - local;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (k < q && i0 + k < nwg) {
+                    sh.pre[i0 + k] = run;
+                    sh.cnt[i0 + k] = cnt[k];
+                    run += cnt[k];
+                }
+            if (threadIdx.x == kWave - 1) {
+                sh.rk = kmin;
+                sh.rz = f;
+                sh.rm = inc;
+            }
+        }
+        __syncthreads();
+        K = sh.rk;
+        Z = sh.rz;
+        M = sh.rm;
+        return;
+    }
+    uint64_t key = kNoKey;
+    uint32_t c = 0, f = 0;
+    if ((int)threadIdx.x < nwg) {
+        key = ld_agent(&rp[threadIdx.x].key);
+        c = ld_agent(&rp[threadIdx.x].count);
+        f = ld_agent(&rp[threadIdx.x].flags);
+    }
+    K = key;
+    Z = f;
+    block_min_or<T>(K, Z, sh.red);
+    if (key == kNoKey || (uint32_t)(key >> 32) != (uint32_t)(K >> 32)) c = 0;
+    const uint32_t pre = block_excl_scan<T>(c, M, sh.red);
+    if ((int)threadIdx.x < nwg) {
+        sh.pre[threadIdx.x] = pre;
+        sh.cnt[threadIdx.x] = c;
+    }
+    __syncthreads();
 }
 
 // Entry e0 + threadIdx.x of the round's bucket, i.e. of the concatenation (in
@@ -261,7 +343,7 @@ __device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const 
         if (sh.pre[mid] <= e) lo_i = mid;
         else hi_i = mid - 1;
     }
-    return rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
+    return ld_agent(&rl[(size_t)lo_i * S + (e - sh.pre[lo_i])]);
 }
 
 // Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
@@ -274,13 +356,14 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                            int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
                            int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
                            int32_t* __restrict__ lists, SharedSolve<T>& sh, SolveStats& st, Ctl* trace,
-                           uint32_t b0 = 0) {
+                           uint32_t epoch, uint32_t b0 = 0) {
     static_assert(T == kCap, "one staged bucket entry per thread");
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
     const Layout lo = make_layout<T>(S);
     Cols<G> cs;
     init_cols(cs, lo, col0, width, src, pred);
+    clear_merge<T>(sh.mrg, 4 * T);
 
     // initial record: the committed state (dist[src] = 0)
     uint32_t cand[G][4];
@@ -290,7 +373,9 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
     uint32_t b = b0;  // barriers passed
     publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)(b & 1) * nwg + g], &lists[((size_t)(b & 1) * nwg + g) * S], sh);
-    bool ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
+    const uint64_t ep = (uint64_t)epoch << 32;
+    ++b;
+    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
 
     bool pending = false;
     uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
@@ -298,11 +383,9 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         const int slot = (b - 1) & 1;
         const Pub* rp = pubs + (size_t)slot * nwg;
         const int32_t* rl = lists + (size_t)slot * nwg * S;
-        Pub rec = {kNoKey, 0, 0};
-        if ((int)threadIdx.x < nwg) rec = rp[threadIdx.x];
-        uint64_t K = rec.key;
-        uint32_t Z = rec.flags;
-        block_min_or<T>(K, Z, sh.red);
+        uint64_t K;
+        uint32_t Z, M_rec;
+        read_records<T>(rp, nwg, sh, K, Z, M_rec);
         if (pending) {
             pending = false;
             if (Z) {
@@ -326,7 +409,8 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 const int ns = b & 1;
                 publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
                               &lists[((size_t)ns * nwg + g) * S], sh);
-                ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
+                ++b;
+                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
                 continue;
             }
             if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
@@ -350,13 +434,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
             stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
-            const uint32_t c = ((int)threadIdx.x < nwg && (uint32_t)(rec.key >> 32) == d) ? rec.count : 0u;
-            const uint32_t pre = block_excl_scan<T>(c, M, sh.red);
-            if ((int)threadIdx.x < nwg) {
-                sh.pre[threadIdx.x] = pre;
-                sh.cnt[threadIdx.x] = c;
-            }
-            __syncthreads();
+            M = M_rec;  // sh.pre / sh.cnt hold the bucket's records (read_records)
             // stage the bucket chunk by chunk; the next chunk's entries are loaded
             // while the current chunk's rows stream
             int32_t nxt = gather_entry<T>(sh, rl, nwg, S, 0, M);
@@ -389,7 +467,8 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         pu0 = u0;
         pbucket = bucket;
         pM = M;
-        ok = gang_barrier<T>(bw, ++b, (uint32_t)nwg, timeout, sh);
+        ++b;
+        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
     }
     if (!ok) st.status |= kStatusTimeout;
     write_dist(cs, lo, col0, width, dist);

@@ -41,6 +41,9 @@ int grid_occupancy(int slice, int* per_cu);
 // columns); lists: 2 * nwg * S 64-bit entries.
 hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, uint64_t* lists,
                      bool plain, hipStream_t s);
+
+// Zeroes `bytes` (a multiple of 4) of device memory with a kernel on stream s.
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t s);
 int lc_occupancy(int slice, int* per_cu);
 
 // One instance of a batched launch or one served query, as the kernels read it.
