@@ -54,13 +54,28 @@ bool aligned(const void* p, int64_t ld, int elem) {
     return ((uintptr_t)p % (4 * (uintptr_t)elem)) == 0 && ld % 4 == 0;
 }
 
-// Items in largest-first order; an instance with n > single_max_n is split
-// into parts of at most gang_columns columns solved by a gang of workgroups.
+// Instances of one matrix shared by at least this many sources fill the GPU by
+// themselves: each is solved by one workgroup (no gang exchange), and they are
+// queued after the other instances, whose gangs are bound by their chains of
+// rounds and start first; the shared ones fill the workgroups the gangs leave.
+constexpr int32_t kSharedSources = 32;
+
+// Items in largest-first order (instances of shared matrices last); an instance
+// with n > single_max_n is split into parts of at most gang_columns columns
+// solved by a gang of workgroups.
 int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t single_max_n,
           int32_t gang_columns, int32_t max_parts, Build* out) {
     std::vector<int32_t> order(count);
     for (int32_t i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return inst[x].n > inst[y].n; });
+    std::map<std::pair<const void*, int64_t>, int32_t> uses;
+    for (int32_t i = 0; i < count; ++i) ++uses[{src[i].W, src[i].ld}];
+    std::vector<char> shared(count);
+    for (int32_t i = 0; i < count; ++i)
+        shared[i] = uses[{src[i].W, src[i].ld}] >= kSharedSources && inst[i].n <= max_batch_single_n();
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        if (shared[x] != shared[y]) return shared[x] < shared[y];
+        return inst[x].n > inst[y].n;
+    });
     out->items.clear();
     out->parts.clear();
     out->arena_bytes = 0;
@@ -77,7 +92,7 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
         b.n = I.n;
         b.src = I.src;
         b.vec = aligned(b.W, b.ld, b.elem) ? 1 : 0;
-        if (I.n <= single_max_n) {
+        if (I.n <= single_max_n || shared[order[k]]) {
             b.parts = 1;
             b.S = I.n;
         } else {
@@ -132,8 +147,10 @@ int make_compact(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, Compact
     if (e != hipSuccess) return hip_err(e, "weight range");
     out->wmin = r[0];
     out->wmax = r[1];
+    // compact keys carry the row in 16 bits: copies only for n <= 65536
     int elem = 4;
-    if (r[0] >= 0 && r[1] <= 254) elem = 1;
+    if (n > 65536) elem = 4;
+    else if (r[0] >= 0 && r[1] <= 254) elem = 1;
     else if (r[0] >= 0 && r[1] <= 65534) elem = 2;
     if (elem == 4) return SSSP_OK;
     const int64_t ldc = ((int64_t)n + 15) & ~int64_t(15);
@@ -356,7 +373,7 @@ int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t fl
         cands.push_back(Cand{tuning->single_max_n, tuning->gang_columns > 0 ? tuning->gang_columns : 4096});
     } else {
         if (nmax <= max_batch_single_n()) cands.push_back(Cand{max_batch_single_n(), 4096});
-        for (int32_t c : {4096, 2048, 1024, 512})
+        for (int32_t c : {4096, 2048, 1024, 512, 256})
             if (c < nmax) cands.push_back(Cand{c, c});
     }
     double best_ms = 1e30;

@@ -191,13 +191,6 @@ __device__ __forceinline__ Layout make_layout(int S) {
     return lo;
 }
 
-// Columns of the slice held by one thread: G groups of 4.
-template <int G>
-struct Cols {
-    uint32_t dist[G][4];
-    uint64_t best[G][4];
-    uint32_t vis;  // bit 4k+j: visited, or not a column of the slice/matrix
-};
 
 // Matrix entries as stored.  int32_t is the caller's matrix (INT32_MAX = no
 // edge).  uint16_t / uint8_t are exact compact copies that the library builds
@@ -213,6 +206,72 @@ template <>
 __device__ __forceinline__ uint32_t widen<uint16_t>(uint32_t v) { return v == 0xffffu ? kInf : v; }
 template <>
 __device__ __forceinline__ uint32_t widen<uint8_t>(uint32_t v) { return v == 0xffu ? kInf : v; }
+
+// Per-column candidate key of a round: the lexicographic minimum over the
+// streamed rows u of (weight, u).  For the caller's int32 matrix a 64-bit key
+// (W[u][v] << 32) | u.  For compact copies (n <= 65536) a 32-bit key
+// (code << 16) | u built from the stored code itself: the no-edge code (all
+// ones) sorts above every weight, so nothing is widened while streaming (3
+// vector operations per entry: extract, shift-or, 32-bit minimum, instead of
+// about 8 with widened 64-bit keys) and a lane's keys take half the registers.
+template <typename E>
+struct KeyOf {
+    typedef uint64_t type;
+};
+template <>
+struct KeyOf<uint16_t> {
+    typedef uint32_t type;
+};
+template <>
+struct KeyOf<uint8_t> {
+    typedef uint32_t type;
+};
+template <typename E>
+using key_t = typename KeyOf<E>::type;
+
+template <typename E>
+__device__ __forceinline__ key_t<E> key_none() {
+    return (key_t<E>)~(key_t<E>)0;
+}
+// Key of an entry as read (the int32 bits, or the compact code) in row u.
+template <typename E>
+__device__ __forceinline__ key_t<E> key_make(uint32_t raw, uint32_t u) {
+    if constexpr (sizeof(E) == 4) return ((uint64_t)raw << 32) | u;
+    else return (raw << 16) | u;
+}
+// Weight of a key: INT32_MAX for no edge (and for the no-key value of compact
+// keys); an int32 key above INT32_MAX holds a negative weight (or is no key).
+template <typename E>
+__device__ __forceinline__ uint32_t key_weight(key_t<E> k) {
+    if constexpr (sizeof(E) == 4) {
+        return (uint32_t)(k >> 32);
+    } else {
+        const uint32_t code = k >> 16;
+        return code >= (uint32_t)(E)~(E)0 ? kInf : code;
+    }
+}
+template <typename E>
+__device__ __forceinline__ uint32_t key_row(key_t<E> k) {
+    if constexpr (sizeof(E) == 4) return (uint32_t)k;
+    else return k & 0xffffu;
+}
+// Entry value standing for "no column here" when a partial group is read.
+template <typename E>
+__device__ __forceinline__ uint32_t absent_code() {
+    return sizeof(E) == 4 ? kInf : 0xffffu;
+}
+template <typename X>
+__device__ __forceinline__ X key_min(X a, X b) {
+    return b < a ? b : a;
+}
+
+// Columns of the slice held by one thread: G groups of 4.
+template <int G, typename E = int32_t>
+struct Cols {
+    uint32_t dist[G][4];
+    key_t<E> best[G][4];
+    uint32_t vis;  // bit 4k+j: visited, or not a column of the slice/matrix
+};
 
 // The matrix always lives in global memory (device or pinned host memory).
 // Descriptors loaded from memory carry generic pointers, which the compiler
@@ -254,19 +313,20 @@ __device__ __forceinline__ void unpack<int32_t>(const v4i& x, uint32_t (&w)[4]) 
     w[2] = (uint32_t)x.z;
     w[3] = (uint32_t)x.w;
 }
+// Compact entries stay as codes (see key_make).
 template <>
 __device__ __forceinline__ void unpack<uint16_t>(const v2u& x, uint32_t (&w)[4]) {
-    w[0] = widen<uint16_t>(x.x & 0xffffu);
-    w[1] = widen<uint16_t>(x.x >> 16);
-    w[2] = widen<uint16_t>(x.y & 0xffffu);
-    w[3] = widen<uint16_t>(x.y >> 16);
+    w[0] = x.x & 0xffffu;
+    w[1] = x.x >> 16;
+    w[2] = x.y & 0xffffu;
+    w[3] = x.y >> 16;
 }
 template <>
 __device__ __forceinline__ void unpack<uint8_t>(const uint32_t& x, uint32_t (&w)[4]) {
-    w[0] = widen<uint8_t>(x & 0xffu);
-    w[1] = widen<uint8_t>((x >> 8) & 0xffu);
-    w[2] = widen<uint8_t>((x >> 16) & 0xffu);
-    w[3] = widen<uint8_t>(x >> 24);
+    w[0] = x & 0xffu;
+    w[1] = (x >> 8) & 0xffu;
+    w[2] = (x >> 16) & 0xffu;
+    w[3] = x >> 24;
 }
 
 // Rows list[r], list[r + P], ... of one column group (4 columns starting at p0
@@ -275,7 +335,7 @@ __device__ __forceinline__ void unpack<uint8_t>(const uint32_t& x, uint32_t (&w)
 // loads carry the nontemporal hint, for matrices streamed once per solve (the
 // whole-GPU solve) rather than reused from the caches across instances.
 template <int U, bool FULL, typename E, bool NT>
-__device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __restrict__ p0, int64_t ld,
+__device__ __forceinline__ void stream_group(key_t<E> (&best)[4], const E* __restrict__ p0, int64_t ld,
                                              int valid, const int32_t* list, int m, int first, int step) {
     for (int i = first; i < m; i += step * U) {
         // past the end of the list, repeat its last row: a duplicate cannot change a minimum
@@ -303,13 +363,13 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __res
             for (int q = 0; q < U; ++q) {
                 const global_ptr<E> p = (global_ptr<E>)p0 + (int64_t)uu[q] * ld;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) w[q][j] = j < valid ? widen<E>((uint32_t)p[j]) : kInf;
+                for (int j = 0; j < 4; ++j) w[q][j] = j < valid ? (uint32_t)p[j] : absent_code<E>();
             }
         }
 #pragma unroll
         for (int q = 0; q < U; ++q)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) best[j] = umin64(best[j], make_key(w[q][j], uu[q]));
+            for (int j = 0; j < 4; ++j) best[j] = key_min(best[j], key_make<E>(w[q][j], uu[q]));
     }
 }
 
@@ -320,7 +380,7 @@ __device__ __forceinline__ void stream_group(uint64_t (&best)[4], const E* __res
 // aligned, ld and the slice start multiples of 4); otherwise, and for a
 // partial last group, entries are read one by one.
 template <int G, int U, typename E, bool NT = false>
-__device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const E* __restrict__ W,
+__device__ __forceinline__ void stream_rows(Cols<G, E>& cs, const Layout& lo, const E* __restrict__ W,
                                             int64_t ld, int64_t col0, int width, bool vec,
                                             const int32_t* list, int m) {
     // One column group at a time keeps only U x 4 weights live per thread.
@@ -341,20 +401,21 @@ __device__ __forceinline__ void stream_rows(Cols<G>& cs, const Layout& lo, const
 // owners read the result and put the all-ones key back.  `mrg` (4 * L keys or
 // more) is all ones between merges (clear_merge at the start of a solve).
 // Only used when P > 1, which implies G == 1.
-template <int T, int G>
-__device__ __forceinline__ void merge_partitions(Cols<G>& cs, const Layout& lo, uint64_t* mrg) {
+template <int T, int G, typename E>
+__device__ __forceinline__ void merge_partitions(Cols<G, E>& cs, const Layout& lo, uint64_t* mrg) {
     if (lo.P == 1) return;
+    key_t<E>* m = reinterpret_cast<key_t<E>*>(mrg);  // all-ones keys of either width
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (cs.best[0][j] != kNoKey)
-            __hip_atomic_fetch_min(&mrg[j * lo.L + lo.c], cs.best[0][j], __ATOMIC_RELAXED,
+        if (cs.best[0][j] != key_none<E>())
+            __hip_atomic_fetch_min(&m[j * lo.L + lo.c], cs.best[0][j], __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
     if (lo.r == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            cs.best[0][j] = mrg[j * lo.L + lo.c];
-            mrg[j * lo.L + lo.c] = kNoKey;
+            cs.best[0][j] = m[j * lo.L + lo.c];
+            m[j * lo.L + lo.c] = key_none<E>();
         }
     }
 }
@@ -398,12 +459,12 @@ __device__ __forceinline__ uint32_t owner_excl_scan(uint32_t x, uint32_t& total,
     return block_excl_scan<T>(x, total, red);
 }
 
-template <int G>
-__device__ __forceinline__ void reset_best(Cols<G>& cs) {
+template <int G, typename E>
+__device__ __forceinline__ void reset_best(Cols<G, E>& cs) {
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cs.best[k][j] = kNoKey;
+        for (int j = 0; j < 4; ++j) cs.best[k][j] = key_none<E>();
 }
 
 // Local vertex index of (k, j) for this thread.
@@ -413,8 +474,8 @@ __device__ __forceinline__ int local_col(const Layout& lo, int k, int j) {
 
 // Initialise the owned columns: dist = inf (0 at the source), not visited;
 // columns past the slice/matrix are flagged visited so they never take part.
-template <int G>
-__device__ __forceinline__ void init_cols(Cols<G>& cs, const Layout& lo, int64_t col0, int width,
+template <int G, typename E>
+__device__ __forceinline__ void init_cols(Cols<G, E>& cs, const Layout& lo, int64_t col0, int width,
                                           int32_t src, int32_t* __restrict__ pred) {
     cs.vis = 0;
 #pragma unroll
@@ -431,8 +492,8 @@ __device__ __forceinline__ void init_cols(Cols<G>& cs, const Layout& lo, int64_t
 }
 
 // Lowest (dist, vertex) key among unvisited owned columns.
-template <int G>
-__device__ __forceinline__ uint64_t local_argmin(const Cols<G>& cs, const Layout& lo, int64_t col0) {
+template <int G, typename E>
+__device__ __forceinline__ uint64_t local_argmin(const Cols<G, E>& cs, const Layout& lo, int64_t col0) {
     uint64_t key = kNoKey;
 #pragma unroll
     for (int k = 0; k < G; ++k)
@@ -444,8 +505,8 @@ __device__ __forceinline__ uint64_t local_argmin(const Cols<G>& cs, const Layout
 }
 
 // Bitmask of unvisited owned columns whose dist equals d (the round's bucket).
-template <int G>
-__device__ __forceinline__ uint32_t bucket_mask(const Cols<G>& cs, uint32_t d) {
+template <int G, typename E>
+__device__ __forceinline__ uint32_t bucket_mask(const Cols<G, E>& cs, uint32_t d) {
     uint32_t m = 0;
 #pragma unroll
     for (int k = 0; k < G; ++k)
@@ -458,10 +519,11 @@ __device__ __forceinline__ uint32_t bucket_mask(const Cols<G>& cs, uint32_t d) {
 // Candidate dist of a column from the round's minimum key (d + min weight);
 // returns kInf + something >= dist when there is no usable edge.  Sets *neg if
 // the minimum weight read as uint32 exceeds INT32_MAX (a negative weight).
-__device__ __forceinline__ uint32_t candidate(uint64_t best, uint32_t d, uint32_t& neg) {
-    const uint32_t w = (uint32_t)(best >> 32);
+template <typename E>
+__device__ __forceinline__ uint32_t candidate(key_t<E> best, uint32_t d, uint32_t& neg) {
+    const uint32_t w = key_weight<E>(best);
     if (w > kInf) {
-        neg |= best != kNoKey ? kStatusNegWeight : 0u;
+        neg |= best != key_none<E>() ? kStatusNegWeight : 0u;
         return 0xffffffffu;
     }
     return d + w;  // d < 2^31-1 and w <= 2^31-1: no wrap
@@ -470,23 +532,23 @@ __device__ __forceinline__ uint32_t candidate(uint64_t best, uint32_t d, uint32_
 // Zero-weight hazard of a fused round: an unvisited vertex outside the bucket
 // (dist > d) reachable from the bucket by a weight-0 edge would join the bucket
 // during the round and change the order Algorithm 1 settles it in.
-template <int G>
-__device__ __forceinline__ uint32_t zero_hazard(const Cols<G>& cs, uint32_t d) {
+template <int G, typename E>
+__device__ __forceinline__ uint32_t zero_hazard(const Cols<G, E>& cs, uint32_t d) {
     uint32_t z = 0;
 #pragma unroll
     for (int k = 0; k < G; ++k)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (!(cs.vis >> (4 * k + j) & 1u) && cs.dist[k][j] > d &&
-                (uint32_t)(cs.best[k][j] >> 32) == 0u)
+                key_weight<E>(cs.best[k][j]) == 0u)
                 z = 1;
     return z;
 }
 
 // Apply a fused round: the bucket (mask) becomes visited; every other unvisited
 // column takes its candidate if strictly smaller (pred = the candidate's row).
-template <int G>
-__device__ __forceinline__ uint32_t commit_fused(Cols<G>& cs, const Layout& lo, int64_t col0,
+template <int G, typename E>
+__device__ __forceinline__ uint32_t commit_fused(Cols<G, E>& cs, const Layout& lo, int64_t col0,
                                                  uint32_t d, uint32_t bucket,
                                                  int32_t* __restrict__ pred) {
     uint32_t neg = 0;
@@ -496,10 +558,10 @@ __device__ __forceinline__ uint32_t commit_fused(Cols<G>& cs, const Layout& lo, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (cs.vis >> (4 * k + j) & 1u) continue;
-            const uint32_t c = candidate(cs.best[k][j], d, neg);
+            const uint32_t c = candidate<E>(cs.best[k][j], d, neg);
             if (c < cs.dist[k][j]) {
                 cs.dist[k][j] = c;
-                pred[col0 + local_col(lo, k, j)] = (int32_t)(uint32_t)cs.best[k][j];
+                pred[col0 + local_col(lo, k, j)] = (int32_t)key_row<E>(cs.best[k][j]);
             }
         }
     reset_best(cs);
@@ -508,18 +570,18 @@ __device__ __forceinline__ uint32_t commit_fused(Cols<G>& cs, const Layout& lo, 
 
 // Would-be dist of a column if the pending fused round were applied (kNoKey-style
 // sentinel 0xffffffff for columns that are visited or in the bucket).
-template <int G>
-__device__ __forceinline__ uint32_t would_be(const Cols<G>& cs, int k, int j, uint32_t d,
+template <int G, typename E>
+__device__ __forceinline__ uint32_t would_be(const Cols<G, E>& cs, int k, int j, uint32_t d,
                                              uint32_t bucket, uint32_t& neg) {
     const uint32_t bit = 1u << (4 * k + j);
     if ((cs.vis | bucket) & bit) return 0xffffffffu;
-    const uint32_t c = candidate(cs.best[k][j], d, neg);
+    const uint32_t c = candidate<E>(cs.best[k][j], d, neg);
     return c < cs.dist[k][j] ? c : cs.dist[k][j];
 }
 
 // Write the owned dist values back (a8: writeback).
-template <int G>
-__device__ __forceinline__ void write_dist(const Cols<G>& cs, const Layout& lo, int64_t col0, int width,
+template <int G, typename E>
+__device__ __forceinline__ void write_dist(const Cols<G, E>& cs, const Layout& lo, int64_t col0, int width,
                                            int32_t* __restrict__ dist) {
     if (lo.r != 0) return;
 #pragma unroll

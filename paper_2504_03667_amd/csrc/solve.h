@@ -52,7 +52,7 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
                              int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec,
                              bool literal, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
     const Layout lo = make_layout<T>(n);
-    Cols<G> cs;
+    Cols<G, E> cs;
     init_cols(cs, lo, 0, n, src, pred);
     clear_merge<T>(sh.mrg, 4 * T);
     for (;;) {
@@ -361,7 +361,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
     const Layout lo = make_layout<T>(S);
-    Cols<G> cs;
+    Cols<G, E> cs;
     init_cols(cs, lo, col0, width, src, pred);
     clear_merge<T>(sh.mrg, 4 * T);
 
