@@ -136,7 +136,10 @@ int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int
  * pointing at device buffers; instances may share W) in ONE persistent launch
  * in which workgroups pull work from a ticket counter, largest instance first:
  * an instance with n <= sssp_batch_max_n() is solved by one workgroup, a
- * larger one by a gang of workgroups that split its columns.  Asynchronous.
+ * larger one by a gang of workgroups that split its columns.  With
+ * SSSP_FLAG_LABEL_CORRECTING every instance whose matrix is not shared by 32
+ * or more instances is solved with the label-correcting method (see that
+ * flag) by a gang of 256-column slices.  Asynchronous.
  */
 int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags,
                              const sssp_tuning* tuning, void* stream);
@@ -153,7 +156,15 @@ int32_t sssp_batch_max_n(void);
  * workgroups that share an instance's columns) unless `tuning` fixes one,
  * keeps the fastest, and captures the launch into a hipGraph.  A launch
  * replays the graph on `stream`: one persistent kernel for all instances.
- * The instance buffers must stay valid while the plan exists.
+ * Instances of a matrix shared by 32 or more instances are always solved by
+ * one workgroup each.  When it measures splits, it also solves each other
+ * distinct matrix once (from its first instance's source, into scratch
+ * buffers): a matrix whose solve takes 64 or more rounds (many distinct
+ * distances) is a candidate for the label-correcting method, which is kept
+ * for those instances if the whole launch is faster with it;
+ * SSSP_FLAG_LABEL_CORRECTING uses it for all of them without measuring.
+ * Results are the same either way.  The instance buffers must stay valid
+ * while the plan exists.
  */
 typedef struct sssp_batch_plan sssp_batch_plan;
 
@@ -167,6 +178,8 @@ typedef struct sssp_plan_info {
     int64_t compact_bytes;               /* device bytes held by the compact copies */
     double tuned_ms;                     /* time of the chosen configuration, -1 if not measured */
     double build_ms;                     /* wall time of sssp_batch_plan_create */
+    int32_t lc_instances;                /* instances solved with the label-correcting method */
+    int32_t lc_candidates;               /* instances whose matrix qualified for it */
 } sssp_plan_info;
 
 int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
@@ -244,7 +257,12 @@ typedef struct sssp_server_config {
     int64_t scratch_bytes;  /* device arena for gang exchange records (0 = 256 MiB) */
     int64_t max_pending;    /* submissions waiting for admission before SSSP_EAGAIN (0 = no limit) */
     int32_t idle_park_ms;   /* kernel leaves after this long with no query; relaunched on demand (0 = 20) */
-    int32_t reserved[7];
+    int32_t lc_rounds;      /* once a query of a graph took this many rounds, later queries of that graph
+                               use the label-correcting method if a cost model of the first such query
+                               (exchanges per round vs rows streamed) finds it cheaper (0 = 64; < 0 = never) */
+    int32_t lc_gang_columns;  /* columns per gang member of label-correcting queries (0 = 1024) */
+    int32_t lc_model;       /* < 0: switch on lc_rounds alone, without the cost model (0 = use it) */
+    int32_t reserved[4];
 } sssp_server_config;
 
 /* query states */
@@ -261,6 +279,8 @@ typedef struct sssp_query_info {
     int64_t t_submit_ns;  /* sssp_server_now_ns() clock */
     int64_t t_admit_ns;
     int64_t t_done_ns;    /* when the host saw the completion record */
+    int32_t method;       /* 0: Dijkstra rounds, 1: label-correcting (rounds = sweeps) */
+    int32_t reserved;
 } sssp_query_info;
 
 typedef struct sssp_server_stats {
@@ -281,7 +301,9 @@ int sssp_server_add_graph(sssp_server* s, const int32_t* W, int64_t ld, int32_t 
 
 /* As sssp_server_add_graph; with SSSP_FLAG_COMPACT the server builds and keeps an
  * exact uint8/uint16 copy of W when its weights fit (see sssp_batch_plan_create)
- * and streams that copy.  Synchronous. */
+ * and streams that copy; with SSSP_FLAG_LABEL_CORRECTING every query of the graph
+ * uses the label-correcting method (otherwise only after one took lc_rounds
+ * rounds).  Same dist/pred either way.  Synchronous. */
 int sssp_server_add_graph_ex(sssp_server* s, const int32_t* W, int64_t ld, int32_t n, uint32_t flags,
                              int32_t* graph_id);
 

@@ -45,7 +45,7 @@ def build(verbose=False):
 
 # The files the whole-GPU solve (its kernel, launch shape and flags) is built from;
 # a profile taken of that kernel stays valid while none of them changes.
-GRID_KERNEL_FILES = ("kernels.hip", "solve.h", "engine.h", "sssp_internal.h", "api.cpp")
+GRID_KERNEL_FILES = ("kernels.hip", "solve.h", "lc.h", "engine.h", "sssp_internal.h", "api.cpp")
 
 
 def source_hash(files=GRID_KERNEL_FILES):

@@ -60,11 +60,16 @@ bool aligned(const void* p, int64_t ld, int elem) {
 // rounds and start first; the shared ones fill the workgroups the gangs leave.
 constexpr int32_t kSharedSources = 32;
 
+// Columns per gang member of a label-correcting instance: its sweeps read 3-5
+// times the rows of a Dijkstra solve, so it is spread over many workgroups.
+constexpr int32_t kLcColumns = 256;
+
 // Items in largest-first order (instances of shared matrices last); an instance
 // with n > single_max_n is split into parts of at most gang_columns columns
-// solved by a gang of workgroups.
+// solved by a gang of workgroups.  lc (may be null): per instance, solve it
+// with the label-correcting method (never for shared matrices).
 int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t single_max_n,
-          int32_t gang_columns, int32_t max_parts, Build* out) {
+          int32_t gang_columns, int32_t max_parts, Build* out, const char* lc = nullptr) {
     std::vector<int32_t> order(count);
     for (int32_t i = 0; i < count; ++i) order[i] = i;
     std::map<std::pair<const void*, int64_t>, int32_t> uses;
@@ -92,12 +97,15 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
         b.n = I.n;
         b.src = I.src;
         b.vec = aligned(b.W, b.ld, b.elem) ? 1 : 0;
-        if (I.n <= single_max_n || shared[order[k]]) {
+        const bool use_lc = lc && lc[order[k]] && !shared[order[k]];
+        b.method = use_lc ? kMethodLabelCorrecting : kMethodDijkstra;
+        if (!use_lc && (I.n <= single_max_n || shared[order[k]])) {
             b.parts = 1;
             b.S = I.n;
         } else {
-            int64_t p = ((int64_t)I.n + gang_columns - 1) / gang_columns;
-            p = std::max<int64_t>(2, std::min<int64_t>(p, max_parts));
+            const int32_t cols = use_lc ? kLcColumns : gang_columns;
+            int64_t p = ((int64_t)I.n + cols - 1) / cols;
+            p = std::max<int64_t>(use_lc ? 1 : 2, std::min<int64_t>(p, max_parts));
             int64_t s = ((int64_t)I.n + p - 1) / p;
             s = (s + 3) & ~int64_t(3);
             if (s > max_batch_slice())
@@ -105,8 +113,7 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
             b.S = (int32_t)s;
             b.parts = (int32_t)(((int64_t)I.n + s - 1) / s);
             b.scratch_off = out->arena_bytes;
-            const uint64_t bytes = 2ull * b.parts * pub_size() + 2ull * b.parts * (uint64_t)b.S * 4;
-            out->arena_bytes += (bytes + 255) & ~uint64_t(255);
+            out->arena_bytes += item_scratch_bytes(b.method, b.parts, b.S, pub_size());
             out->max_parts = std::max(out->max_parts, b.parts);
         }
         for (int32_t j = 0; j < b.parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
@@ -179,6 +186,7 @@ struct sssp_batch_plan {
     std::vector<sssp_instance> inst;
     std::vector<Source> src;
     std::vector<CompactCopy> copies;
+    std::vector<char> lc;  // per instance: label-correcting (empty: none)
     BatchItem* d_items = nullptr;
     BatchPart* d_parts = nullptr;
     int32_t nparts = 0;
@@ -206,8 +214,10 @@ struct sssp_batch_plan {
     int upload(int32_t single_max_n, int32_t gang_columns) {
         Build b;
         int rc = ::build(inst.data(), src.data(), (int32_t)inst.size(), single_max_n, gang_columns,
-                         std::max(2, nwg / 2), &b);
+                         std::max(2, nwg / 2), &b, lc.empty() ? nullptr : lc.data());
         if (rc) return rc;
+        lc_items = 0;
+        for (const BatchItem& it : b.items) lc_items += it.method == kMethodLabelCorrecting;
         free_device();
         hipError_t e = hipMalloc(&d_items, sizeof(BatchItem) * b.items.size());
         if (e == hipSuccess) e = hipMalloc(&d_parts, sizeof(BatchPart) * b.parts.size());
@@ -230,7 +240,72 @@ struct sssp_batch_plan {
         return launch_batch(d_items, d_parts, nparts, d_bars, d_arena, flags & SSSP_FLAG_LITERAL,
                             clock_khz * 10000, d_ctl, nwg, s);
     }
+
+    int32_t lc_items = 0;
+
+    // Median-free timing of the uploaded configuration: best of 2 launches after a
+    // warm-up (ms), or a negative value on a launch error (e set).
+    float time_launches(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipError_t& e) {
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(ev0, s);
+            e = enqueue(s);
+            (void)hipEventRecord(ev1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            if (e != hipSuccess) return -1.0f;
+            float t = 0;
+            (void)hipEventElapsedTime(&t, ev0, ev1);
+            if (rep > 0) ms = std::min(ms, t);  // first run warms caches
+        }
+        return ms;
+    }
 };
+
+namespace {
+
+// Rounds of a Dijkstra solve from which a matrix is tried with the
+// label-correcting method: with that many distinct distances the rounds'
+// exchanges, not the bytes, bound its instances.
+constexpr int64_t kLcRounds = 64;
+
+// Marks p->lc for every instance of a distinct matrix (used by fewer than
+// kSharedSources instances) whose solve from its first instance's source takes
+// kLcRounds rounds or more; the solves write into scratch buffers.  With
+// SSSP_FLAG_LABEL_CORRECTING nothing is measured.
+int lc_candidates(sssp_batch_plan* p, hipStream_t s) {
+    p->lc.clear();
+    p->info.lc_candidates = 0;
+    if (p->flags & (SSSP_FLAG_LABEL_CORRECTING | SSSP_FLAG_LITERAL)) return SSSP_OK;
+    const int32_t count = (int32_t)p->inst.size();
+    std::map<std::pair<const int32_t*, int64_t>, std::vector<int32_t>> by_matrix;
+    for (int32_t i = 0; i < count; ++i) by_matrix[{p->inst[i].W, p->inst[i].ld}].push_back(i);
+    int32_t nmax = 0;
+    for (const auto& I : p->inst) nmax = std::max(nmax, I.n);
+    int32_t* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, 2 * sizeof(int32_t) * (size_t)nmax);
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc(probe buffers): %s", hipGetErrorString(e));
+    std::vector<char> lc(count, 0);
+    int rc = SSSP_OK;
+    for (const auto& kv : by_matrix) {
+        if ((int32_t)kv.second.size() >= kSharedSources) continue;
+        const sssp_instance& I = p->inst[kv.second.front()];
+        rc = sssp_dense_solve_ex(I.W, I.ld, I.n, I.src, buf, buf + nmax, 0u, nullptr, s);
+        int32_t status = 0;
+        int64_t stats[kStatCount] = {0};
+        if (rc == SSSP_OK) rc = sssp_last_status(s, &status, stats);
+        if (rc != SSSP_OK) break;
+        if (stats[kStatRounds] >= kLcRounds)
+            for (int32_t i : kv.second) lc[i] = 1;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (rc != SSSP_OK) return rc;
+    for (char c : lc) p->info.lc_candidates += c;
+    if (p->info.lc_candidates > 0) p->lc = lc;
+    return SSSP_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -273,7 +348,10 @@ int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t 
     std::vector<Source> src(count);
     for (int32_t i = 0; i < count; ++i) src[i] = Source{inst[i].W, inst[i].ld, 4};
     Build b;
-    rc = build(inst, src.data(), count, max_batch_single_n(), 4096, std::max(2, nwg / 2), &b);
+    std::vector<char> lc;
+    if (flags & SSSP_FLAG_LABEL_CORRECTING) lc.assign(count, 1);
+    rc = build(inst, src.data(), count, max_batch_single_n(), 4096, std::max(2, nwg / 2), &b,
+               lc.empty() ? nullptr : lc.data());
     if (rc) return rc;
     nwg = std::max(1, std::min<int>(nwg, (int)b.parts.size()));
     if (nwg < b.max_parts) nwg = b.max_parts;
@@ -385,17 +463,7 @@ int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t fl
         for (const Cand& c : cands) {
             rc = p->upload(c.single_max_n, c.gang_columns);
             if (rc) continue;
-            float ms = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                (void)hipEventRecord(ev0, s);
-                e = p->enqueue(s);
-                (void)hipEventRecord(ev1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(ev1);
-                if (e != hipSuccess) break;
-                float t = 0;
-                (void)hipEventElapsedTime(&t, ev0, ev1);
-                if (rep > 0) ms = std::min(ms, t);  // first run warms caches
-            }
+            const float ms = p->time_launches(s, ev0, ev1, e);
             if (e != hipSuccess) {
                 (void)hipEventDestroy(ev0);
                 (void)hipEventDestroy(ev1);
@@ -407,11 +475,35 @@ int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t fl
                 best = c;
             }
         }
+        // label-correcting candidates: distinct matrices (not shared by many
+        // instances) whose solve needs many rounds; kept if the launch is faster
+        rc = lc_candidates(p, s);
+        if (rc) {
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+            return fail(rc);
+        }
+        if (p->info.lc_candidates > 0) {
+            rc = p->upload(best.single_max_n, best.gang_columns);
+            float ms = rc ? -1.0f : p->time_launches(s, ev0, ev1, e);
+            if (rc == 0 && e != hipSuccess) {
+                (void)hipEventDestroy(ev0);
+                (void)hipEventDestroy(ev1);
+                return fail(hip_err(e, "autotuning launch"));
+            }
+            p->info.candidates += 1;
+            if (ms >= 0 && ms < best_ms) best_ms = ms;
+            else p->lc.clear();
+        }
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
+    } else if (flags & SSSP_FLAG_LABEL_CORRECTING) {
+        p->lc.assign(count, 1);
     }
+    if (flags & SSSP_FLAG_LABEL_CORRECTING) p->lc.assign(count, 1);
     rc = p->upload(best.single_max_n, best.gang_columns);
     if (rc) return fail(rc);
+    p->info.lc_instances = p->lc_items;
     p->info.threads = 1024;
     p->info.workgroups = p->nwg;
     p->info.single_max_n = best.single_max_n;

@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "engine.h"
+#include "lc.h"
 #include "solve.h"
 #include "sssp_internal.h"
 
@@ -72,10 +73,18 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
 // ---------------------------------------------------------------------------
 // Each (matrix type, columns-per-thread) variant is compiled as a function of
 // its own, so that its register allocation does not pay for the others.
+// Rows in flight per thread.  More rows keep more bytes in flight for compact
+// entries, but a thread pads the last batch of a bucket with copies of its last
+// row, and the small buckets of sparse graphs made 16 rows slower overall
+// (batched workload 3.6 -> 4.1 ms, served saturation -14%): 8 for every type.
+template <typename E>
+constexpr int rows_in_flight() { return 8; }
+
 template <int T, int G, typename E>
 __device__ __attribute__((noinline)) SolveStats single_variant(BatchItem I, bool literal) {
     SolveStats st = {0, 0, 0, 0, 0};
-    solve_single<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, literal,
+    solve_single<T, G, rows_in_flight<E>(), E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
+                                              I.vec != 0, literal,
                              g_sh<T>, st, nullptr);
     uint32_t s = st.status;
     uint64_t dummy = kNoKey;
@@ -90,10 +99,51 @@ __device__ __attribute__((noinline)) SolveStats gang_variant(BatchItem I, int pa
     SolveStats st = {0, 0, 0, 0, 0};
     Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
     int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * I.parts);
-    solve_gang<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, literal, I.S,
+    solve_gang<T, G, rows_in_flight<E>(), E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
+                                            I.vec != 0, literal, I.S,
                            part, I.parts, timeout, bw, pubs, lists, g_sh<T>, st, nullptr, epoch);
     if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
     return st;
+}
+
+// A label-correcting item (rank `part` of a gang of I.parts, possibly one): the
+// sweeps, then the pred pass; a tight zero-weight edge sends the whole gang to
+// the Dijkstra rounds on the same records (numbering continued).
+template <int T, int G, typename E>
+__device__ __attribute__((noinline)) SolveStats lc_variant(BatchItem I, int part, long long timeout, Bar* bw,
+                                                           char* arena, uint32_t epoch) {
+    SolveStats st = {0, 0, 0, 0, 0};
+    Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
+    uint64_t* lists = reinterpret_cast<uint64_t*>(pubs + 2 * I.parts);
+    uint32_t b = 0;
+    const int r = solve_lc<T, G, 8, E, false>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
+                                              I.vec != 0, I.S, part, I.parts, timeout, bw, pubs, lists, g_sh<T>,
+                                              g_lc<T>, st, b, epoch, nullptr);
+    if (r == kLcFallback) {
+        ++st.fallbacks;
+        st.status |= kStatusZeroFallback;
+        solve_gang<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, false,
+                               I.S, part, I.parts, timeout, bw, pubs, reinterpret_cast<int32_t*>(lists), g_sh<T>,
+                               st, nullptr, epoch, b);
+    } else {
+        if (r == kLcTimeout) st.status |= kStatusTimeout;
+        st.barriers += b;
+    }
+    if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
+    uint32_t s = st.status;
+    uint64_t dummy = kNoKey;
+    block_min_or<T>(dummy, s, g_sh<T>.red);
+    st.status = s;
+    return st;
+}
+
+template <int T, typename E>
+__device__ __forceinline__ SolveStats lc_by_size(const BatchItem& I, int part, long long timeout, Bar* bw,
+                                                 char* arena, uint32_t epoch) {
+    const int groups = (I.S + 3) / 4;
+    if (groups <= T) return lc_variant<T, 1, E>(I, part, timeout, bw, arena, epoch);
+    if (groups <= 2 * T) return lc_variant<T, 2, E>(I, part, timeout, bw, arena, epoch);
+    return lc_variant<T, 4, E>(I, part, timeout, bw, arena, epoch);
 }
 
 template <int T, typename E>
@@ -117,6 +167,11 @@ template <int T>
 // epoch: unique to this use of the item's exchange records (see gang_exchange).
 __device__ __forceinline__ SolveStats solve_item(const BatchItem& I, int part, bool literal, long long timeout,
                                                  Bar* bw, char* arena, uint32_t epoch) {
+    if (I.method == kMethodLabelCorrecting && !literal) {
+        if (I.elem == 1) return lc_by_size<T, uint8_t>(I, part, timeout, bw, arena, epoch);
+        if (I.elem == 2) return lc_by_size<T, uint16_t>(I, part, timeout, bw, arena, epoch);
+        return lc_by_size<T, int32_t>(I, part, timeout, bw, arena, epoch);
+    }
     if (I.parts <= 1) {
         if (I.elem == 1) return single_by_size<T, uint8_t>(I, literal);
         if (I.elem == 2) return single_by_size<T, uint16_t>(I, literal);

@@ -60,6 +60,9 @@ struct Graph {
     int64_t lds;
     int32_t elem;
     void* owned;       // compact copy to free on destroy
+    int32_t lc_forced = 0;   // every query label-correcting
+    int32_t max_rounds = 0;  // most rounds a completed Dijkstra query of it took
+    int32_t lc_cheaper = -1; // cost model on its first completed Dijkstra query (-1: none yet)
 };
 
 enum { kPending = 0, kRunning = 1, kDone = 2 };
@@ -70,6 +73,7 @@ struct Query {
     int32_t* pred;
     int32_t state = kPending;
     int32_t parts = 1, S = 0;
+    int32_t method = kMethodDijkstra;
     int32_t qslot = -1;
     uint64_t off = 0, bytes = 0;
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
@@ -168,16 +172,20 @@ struct sssp_server {
         return a;
     }
 
-    // columns per gang member and number of members for an n-vertex query
-    void plan(int32_t n, int32_t* parts, int32_t* S) const {
-        if (n <= cfg.single_max_n) {
+    // columns per gang member and number of members for an n-vertex query;
+    // label-correcting queries are spread over narrow slices (their sweeps read
+    // several times the rows of a Dijkstra solve)
+    void plan(int32_t n, int32_t method, int32_t* parts, int32_t* S) const {
+        const bool lc = method == kMethodLabelCorrecting;
+        if (!lc && n <= cfg.single_max_n) {
             *parts = 1;
             *S = n;
             return;
         }
-        int64_t p = ((int64_t)n + cfg.gang_columns - 1) / cfg.gang_columns;
+        const int32_t cols = lc ? cfg.lc_gang_columns : cfg.gang_columns;
+        int64_t p = ((int64_t)n + cols - 1) / cols;
         const int64_t pmin = ((int64_t)n + max_serve_slice() - 1) / max_serve_slice();
-        p = std::max<int64_t>(p, std::max<int64_t>(2, pmin));
+        p = std::max<int64_t>(p, std::max<int64_t>(lc ? 1 : 2, pmin));
         p = std::min<int64_t>(p, std::max(2, nwg / 2));
         int64_t s = ((int64_t)n + p - 1) / p;
         s = (s + 3) & ~int64_t(3);
@@ -185,10 +193,24 @@ struct sssp_server {
         *S = (int32_t)s;
     }
 
-    static uint64_t footprint(int32_t parts, int32_t S) {
-        if (parts <= 1) return 0;
-        const uint64_t b = 2ull * parts * pub_size() + 2ull * parts * (uint64_t)S * sizeof(int32_t);
-        return (b + 255) & ~uint64_t(255);
+    // Workgroup time of a query of g, from a completed Dijkstra query q: the
+    // rounds' exchanges (about 5 us per round for one workgroup, 8 us per member
+    // and round for a gang) plus its rows at about 25 GB/s per workgroup; a
+    // label-correcting solve is taken as 24 sweeps and 5x the rows (repeated
+    // relaxations and the pred pass).  True when label-correcting is clearly
+    // cheaper, which also keeps saturation throughput from dropping.
+    bool lc_cheaper(const Graph& g, const Query& q) const {
+        const double row_us = (double)g.n * g.elem / 25e3;  // bytes / (25 GB/s) in us
+        const double round_us = q.parts > 1 ? 8.0 : 5.0;
+        const double t_dij = (double)q.parts * q.rounds * round_us + (double)q.settled * row_us;
+        int32_t parts_lc = 1, S_lc = 0;
+        plan(g.n, kMethodLabelCorrecting, &parts_lc, &S_lc);
+        const double t_lc = (double)parts_lc * 24 * 8.0 + 5.0 * (double)q.settled * row_us;
+        return t_lc < 0.8 * t_dij;
+    }
+
+    static uint64_t footprint(int32_t method, int32_t parts, int32_t S) {
+        return item_scratch_bytes(method, parts, S, pub_size());
     }
 
     // publish as many pending queries as fit; caller holds mu
@@ -222,6 +244,7 @@ struct sssp_server {
                 it.src = q.src;
                 it.parts = q.parts;
                 it.S = q.S;
+                it.method = q.method;
                 it.scratch_off = off;
                 d.part = j;
                 d.qslot = (uint32_t)qs;
@@ -252,6 +275,11 @@ struct sssp_server {
             q.status = (int32_t)done[qs].status;
             q.rounds = (int32_t)done[qs].rounds;
             q.settled = (int64_t)done[qs].settled;
+            if (q.method == kMethodDijkstra) {
+                Graph& g = graphs[q.graph];
+                g.max_rounds = std::max(g.max_rounds, q.rounds);
+                if (g.lc_cheaper < 0) g.lc_cheaper = lc_cheaper(g, q) ? 1 : 0;
+            }
             q.state = kDone;
             if (q.bytes) arena_alloc.release(q.off, q.bytes);
             ring_used -= q.parts;
@@ -375,6 +403,9 @@ int sssp_server_create(const sssp_server_config* cfg_in, sssp_server** out) {
     if (c.scratch_bytes <= 0) c.scratch_bytes = 256ll << 20;
     if (c.watchdog_ms <= 0) c.watchdog_ms = 2000;
     if (c.idle_park_ms <= 0) c.idle_park_ms = 20;
+    if (c.lc_rounds == 0) c.lc_rounds = 64;
+    if (c.lc_gang_columns <= 0) c.lc_gang_columns = 1024;
+    c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
     if (c.single_max_n > max_serve_single_n() || c.gang_columns > max_serve_slice() || c.gang_columns % 4)
         return release_all(s), err(SSSP_EINVAL, "single_max_n <= %d and gang_columns <= %d (multiple of 4) required",
                                    max_serve_single_n(), max_serve_slice());
@@ -417,7 +448,7 @@ int sssp_server_add_graph_ex(sssp_server* s, const int32_t* W, int64_t ld, int32
     {
         std::lock_guard<std::mutex> lk(s->mu);
         int32_t parts, S;
-        s->plan(n, &parts, &S);
+        s->plan(n, kMethodDijkstra, &parts, &S);
         if (S > max_serve_slice()) return err(SSSP_EUNSUPPORTED, "n=%d is too large for this server", n);
     }
     Graph g{W, ld, n, W, ld, 4, nullptr};
@@ -432,6 +463,7 @@ int sssp_server_add_graph_ex(sssp_server* s, const int32_t* W, int64_t ld, int32
         if (rc) return rc;
         if (c.elem < 4) g = Graph{W, ld, n, c.data, c.ld, c.elem, c.data};
     }
+    g.lc_forced = (flags & SSSP_FLAG_LABEL_CORRECTING) ? 1 : 0;
     std::lock_guard<std::mutex> lk(s->mu);
     s->graphs.push_back(g);
     *graph_id = (int32_t)s->graphs.size() - 1;
@@ -465,8 +497,13 @@ int sssp_server_submit(sssp_server* s, int32_t graph_id, int32_t src, int32_t* d
     q.src = src;
     q.dist = dist;
     q.pred = pred;
-    s->plan(g.n, &q.parts, &q.S);
-    q.bytes = sssp_server::footprint(q.parts, q.S);
+    // label-correcting: forced for the graph, or its solves take many rounds and
+    // the cost model (unless switched off) finds it cheaper
+    const bool lc = g.lc_forced ||
+                    (s->cfg.lc_rounds > 0 && g.max_rounds >= s->cfg.lc_rounds && (s->cfg.lc_model < 0 || g.lc_cheaper == 1));
+    q.method = lc ? kMethodLabelCorrecting : kMethodDijkstra;
+    s->plan(g.n, q.method, &q.parts, &q.S);
+    q.bytes = sssp_server::footprint(q.method, q.parts, q.S);
     if (q.bytes > (uint64_t)s->cfg.scratch_bytes)
         return err(SSSP_ENOMEM, "query needs %llu scratch bytes, arena has %lld", (unsigned long long)q.bytes,
                    (long long)s->cfg.scratch_bytes);
@@ -517,6 +554,8 @@ int sssp_server_query_info(sssp_server* s, uint64_t ticket, sssp_query_info* inf
     info->t_submit_ns = q.t_submit;
     info->t_admit_ns = q.t_admit;
     info->t_done_ns = q.t_done;
+    info->method = q.method;
+    info->reserved = 0;
     return SSSP_OK;
 }
 

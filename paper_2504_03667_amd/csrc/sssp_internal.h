@@ -58,8 +58,24 @@ struct BatchItem {
     int32_t vec;         // rows aligned for whole-group loads
     int32_t parts;       // workgroups that solve it (1: one workgroup alone; > 1: a gang)
     int32_t S;           // columns per gang member
+    int32_t method;      // kMethodDijkstra or kMethodLabelCorrecting
+    int32_t pad;
     unsigned long long scratch_off;  // byte offset of a gang's records and lists in the arena
 };
+
+// BatchItem::method.  Label-correcting items always run as a gang (possibly of
+// one) with exchange records and 64-bit lists in the arena.
+constexpr int32_t kMethodDijkstra = 0;
+constexpr int32_t kMethodLabelCorrecting = 1;
+
+// Arena bytes of an item's exchange records and lists (0 for a Dijkstra item
+// solved by one workgroup).
+inline unsigned long long item_scratch_bytes(int32_t method, int32_t parts, int32_t S, size_t pub_bytes) {
+    if (method == kMethodDijkstra && parts <= 1) return 0;
+    const unsigned long long entry = method == kMethodLabelCorrecting ? 8 : 4;
+    const unsigned long long b = 2ull * parts * pub_bytes + 2ull * parts * (unsigned long long)S * entry;
+    return (b + 255) & ~255ull;
+}
 
 // Ticket t of a batched launch is part parts[t].part of item parts[t].item;
 // the parts of one item are consecutive.

@@ -55,7 +55,8 @@ class sssp_plan_info(ctypes.Structure):
                 ("max_parts", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("compact_graphs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("compact_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_double),
-                ("build_ms", ctypes.c_double)]
+                ("build_ms", ctypes.c_double), ("lc_instances", ctypes.c_int32),
+                ("lc_candidates", ctypes.c_int32)]
 
 
 class sssp_instance(ctypes.Structure):
@@ -68,14 +69,16 @@ class sssp_server_config(ctypes.Structure):
                 ("max_inflight", ctypes.c_int32), ("single_max_n", ctypes.c_int32),
                 ("gang_columns", ctypes.c_int32), ("watchdog_ms", ctypes.c_int32),
                 ("scratch_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int64),
-                ("idle_park_ms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("idle_park_ms", ctypes.c_int32), ("lc_rounds", ctypes.c_int32),
+                ("lc_gang_columns", ctypes.c_int32), ("lc_model", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class sssp_query_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("parts", ctypes.c_int32),
                 ("rounds", ctypes.c_int32), ("settled", ctypes.c_int64),
                 ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
-                ("t_done_ns", ctypes.c_int64)]
+                ("t_done_ns", ctypes.c_int64), ("method", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sssp_server_stats(ctypes.Structure):

@@ -170,3 +170,47 @@ def test_batched_workload_plan(sp):
         dr, pr, _ = oracle.dijkstra(host[gi], src)
         _, _, d, p = items[k]
         assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), k
+
+
+def test_plans_label_correcting(sp):
+    """Every instance through the label-correcting items (int32 and compact, with a
+    zero-weight graph that forces the in-gang fallback), and the one-shot call."""
+    rng = np.random.default_rng(305)
+    graphs = [random_dense(rng, n, pr, 1, hi, directed=bool(i % 2), zero_prob=0.05 if i == 1 else 0.0)
+              for i, (n, pr, hi) in enumerate([(700, 0.01, 1000), (1200, 0.05, 20), (2500, 0.003, 1000),
+                                               (64, 0.3, 9), (300, 0.02, 60000)])]
+    dev, items, refs = make_items(rng, graphs)
+    cache = {}
+    for flags in (sp.SSSP_FLAG_LABEL_CORRECTING, sp.SSSP_FLAG_LABEL_CORRECTING | sp.SSSP_FLAG_COMPACT):
+        poison(items)
+        with sp.BatchPlan(items, flags) as plan:
+            plan.launch()
+            status, stats = plan.status()
+            assert status & 3 == 0, (flags, status)
+            assert plan.info()["lc_instances"] == len(items)
+            check_items(graphs, items, refs, cache)
+    poison(items)
+    sp.sssp_dense_solve_batched(items, sp.SSSP_FLAG_LABEL_CORRECTING)
+    status, _ = sp.sssp_last_status()
+    assert status & 3 == 0
+    check_items(graphs, items, refs, cache)
+
+
+def test_plan_chooses_label_correcting_for_many_levels(sp):
+    """Sparse graphs with wide weights need hundreds of rounds: the plan measures them
+    as candidates; whatever it keeps, the results are exact."""
+    rng = np.random.default_rng(306)
+    graphs = [gen.dense_host(gen.GraphSpec(n, p, 1, 1000, 900 + i))
+              for i, (n, p) in enumerate([(3000, 0.002), (2000, 0.003), (800, 0.3)])]
+    dev, items, refs = make_items(rng, graphs)
+    for flags in (0, sp.SSSP_FLAG_COMPACT):
+        poison(items)
+        with sp.BatchPlan(items, flags) as plan:
+            plan.launch()
+            status, _ = plan.status()
+            info = plan.info()
+            assert status & 3 == 0
+            sparse = sum(1 for gi, _ in refs if gi < 2)  # instances of the two sparse graphs
+            assert info["lc_candidates"] == sparse
+            assert info["lc_instances"] in (0, sparse)
+            check_items(graphs, items, refs, {})

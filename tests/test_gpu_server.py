@@ -181,3 +181,32 @@ def test_server_compact_graphs(sp):
             srv.wait(t, timeout_s=60)
             dr, pr, _ = oracle.dijkstra(graphs[g], src)
             assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr)
+
+
+def test_server_label_correcting(sp):
+    """Graphs added with SSSP_FLAG_LABEL_CORRECTING, and a server that switches a graph
+    to label-correcting after its first query (lc_rounds=1): every query exact."""
+    rng = np.random.default_rng(207)
+    graphs = make_graphs(rng, [40, 900, 1700, 2600])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    cases = []
+    for k in range(40):
+        g = int(rng.integers(0, len(graphs)))
+        cases.append((g, int(rng.integers(0, graphs[g].shape[0])), *outputs(graphs[g].shape[0])))
+    for forced, cfg in ((True, {}), (False, dict(lc_rounds=1, lc_gang_columns=128, lc_model=-1))):
+        with sp.Server(**cfg) as srv:
+            flags = sp.SSSP_FLAG_LABEL_CORRECTING if forced else 0
+            gids = [srv.add_graph(W, flags | (sp.SSSP_FLAG_COMPACT if i % 2 else 0)) for i, W in enumerate(dev)]
+            if not forced:
+                # one query per graph first: afterwards every graph has taken >= 1 round
+                first = [srv.submit(gids[g], 0, *outputs(graphs[g].shape[0])) for g in range(len(graphs))]
+                for t in first:
+                    srv.wait(t, timeout_s=60)
+                    assert srv.info(t)["method"] == 0
+            jobs = [(g, src, d, p, srv.submit(gids[g], src, d, p)) for g, src, d, p in cases]
+            for g, src, d, p, t in jobs:
+                srv.wait(t, timeout_s=60)
+                info = srv.info(t)
+                assert info["status"] & 3 == 0 and info["method"] == 1, (forced, info)
+                dr, pr, _ = oracle.dijkstra(graphs[g], src)
+                assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), (forced, g, src)
