@@ -105,6 +105,9 @@ def _host_lib():
         lib.gen_entry_c.restype = ctypes.c_int32
         lib.gen_mix64_c.argtypes = [ctypes.c_uint64]
         lib.gen_mix64_c.restype = ctypes.c_uint64
+        lib.gen_sparse_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.gen_sparse_edges.restype = ctypes.c_int
         _host = lib
     return _host
 
@@ -243,6 +246,27 @@ def checksum_device(Wt):
     return int(v.value)
 
 
+def sparse_edges(n, m, lo, hi, seed):
+    """The seeded edge list (u, v, w) of a sparse graph: m edges among n vertices
+    (see gen_sparse_edges in gen_host.c); numpy int32 arrays."""
+    eu = np.empty(m, np.int32)
+    ev = np.empty(m, np.int32)
+    ew = np.empty(m, np.int32)
+    if _host_lib().gen_sparse_edges(n, m, lo, hi, seed, eu.ctypes.data, ev.ctypes.data, ew.ctypes.data) != 0:
+        raise ValueError("bad sparse graph parameters")
+    return eu, ev, ew
+
+
+@dataclass
+class SparseSpec:
+    n: int
+    m: int          # edges drawn (an undirected graph stores each in both orientations)
+    lo: int
+    hi: int
+    seed: int
+    directed: bool = False
+
+
 # ---------------------------------------------------------------------------
 # Workload manifests.  Base seed S; workload k uses S + k.
 # ---------------------------------------------------------------------------
@@ -319,3 +343,11 @@ def workload_serving(n_graphs=32, n_queries=20000, rate_qps=2000.0):
         t += -math.log(1.0 - st.uniform()) / rate_qps
         qs.append(Query(g, s, t))
     return Workload("served_32graphs_20000q_2000qps", graphs, queries=qs)
+
+
+def workload_sparse():
+    """The paper's sparse family (m = 3n undirected edges; Section IV-A lists
+    n = 10000, 20000, 40000), weights in [1, 1000], source 0, plus n = 10^6 with
+    m = 3 * 10^6, far beyond what an n x n matrix could hold."""
+    specs = [SparseSpec(n, 3 * n, 1, 1000, SEED_BASE + 7 + k) for k, n in enumerate((10000, 20000, 40000, 1000000))]
+    return Workload("sparse_m3n", [], [(k, 0) for k in range(len(specs))]), specs

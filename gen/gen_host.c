@@ -154,3 +154,27 @@ uint64_t gen_dense_checksum(const int32_t* W, int64_t ld, int32_t n, int32_t thr
     gen_run(&jb, threads, gen_sum_worker, &s);
     return s;
 }
+
+/*
+ * Seeded edge list of a sparse graph (the paper's sparse family, Section IV-A:
+ * m edges among n vertices).  Edge e, 0 <= e < m, is a pure function of
+ * (seed, e):
+ *   h = mix(mix(seed) ^ (e | 2^63)),  u = (hi32(h) * n) >> 32,  v = (lo32(h) * n) >> 32,
+ *   w = lo + ((lo32(mix(h)) * (hi - lo + 1)) >> 32).
+ * A pair may repeat and u may equal v; the conversion to a matrix or to CSR
+ * keeps a repeated pair's smallest weight and ignores self-loops.
+ */
+int gen_sparse_edges(int32_t n, int64_t m, int32_t lo, int32_t hi, uint64_t seed,
+                     int32_t* eu, int32_t* ev, int32_t* ew)
+{
+    if (n < 1 || m < 0 || hi < lo || !eu || !ev || !ew) return -1;
+    const uint64_t smix = gen_mix64(seed), span = (uint64_t)((int64_t)hi - lo + 1);
+    for (int64_t e = 0; e < m; ++e) {
+        const uint64_t h = gen_mix64(smix ^ ((uint64_t)e | (1ULL << 63)));
+        eu[e] = (int32_t)(((h >> 32) * (uint64_t)n) >> 32);
+        ev[e] = (int32_t)(((h & 0xffffffffULL) * (uint64_t)n) >> 32);
+        const uint64_t h2 = gen_mix64(h);
+        ew[e] = (int32_t)(lo + (uint32_t)(((h2 & 0xffffffffULL) * span) >> 32));
+    }
+    return 0;
+}

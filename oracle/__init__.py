@@ -59,6 +59,13 @@ def lib():
         L.oracle_label_correcting.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P,
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.oracle_label_correcting.restype = ctypes.c_int
+        L.oracle_dijkstra_csr.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P]
+        L.oracle_dijkstra_csr.restype = ctypes.c_int64
+        L.oracle_certificate_csr.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
+                                             ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_certificate_csr.restype = ctypes.c_int
+        L.oracle_closed_form_pred_csr.argtypes = [P, P, P, ctypes.c_int32, P, P]
+        L.oracle_closed_form_pred_csr.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -177,3 +184,61 @@ def label_correcting(W, src):
                                      ctypes.byref(rows)) != 0:
         raise ValueError("bad arguments")
     return dist, int(sw.value), int(rows.value)
+
+
+def _csr(row_ptr, col, w):
+    return (np.ascontiguousarray(row_ptr, np.int64), np.ascontiguousarray(col, np.int32),
+            np.ascontiguousarray(w, np.int32))
+
+
+def dijkstra_csr(row_ptr, col, w, src):
+    """Algorithm 1 over adjacency lists: returns (dist, pred, relaxed_rows)."""
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    n = row_ptr.size - 1
+    dist = np.empty(n, np.int32)
+    pred = np.empty(n, np.int32)
+    r = lib().oracle_dijkstra_csr(row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data, n, src,
+                                  dist.ctypes.data, pred.ctypes.data)
+    if r < 0:
+        raise ValueError("bad arguments")
+    return dist, pred, int(r)
+
+
+def certificate_csr(row_ptr, col, w, src, dist, pred):
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    dist = np.ascontiguousarray(dist, np.int32)
+    pred = np.ascontiguousarray(pred, np.int32)
+    where = ctypes.c_int64(-1)
+    code = lib().oracle_certificate_csr(row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data, row_ptr.size - 1,
+                                        src, dist.ctypes.data, pred.ctypes.data, ctypes.byref(where))
+    if code < 0:
+        raise ValueError("bad arguments")
+    return code, int(where.value)
+
+
+def closed_form_pred_csr(row_ptr, col, w, dist):
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    dist = np.ascontiguousarray(dist, np.int32)
+    pred = np.empty(row_ptr.size - 1, np.int32)
+    if lib().oracle_closed_form_pred_csr(row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                                         row_ptr.size - 1, dist.ctypes.data, pred.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return pred
+
+
+def edges_to_csr(eu, ev, ew, n, directed=False):
+    """Adjacency lists of an edge list, in edge order (an undirected edge gives
+    u -> v then v -> u); edges with an endpoint outside [0, n) are dropped.
+    Plain numpy bookkeeping; duplicates and self-loops are kept (the CSR
+    functions ignore self-loops and take a pair's smallest weight)."""
+    eu = np.asarray(eu, np.int64)
+    ev = np.asarray(ev, np.int64)
+    ew = np.asarray(ew, np.int32)
+    ok = (eu >= 0) & (eu < n) & (ev >= 0) & (ev < n)
+    eu, ev, ew = eu[ok], ev[ok], ew[ok]
+    if not directed:
+        eu, ev, ew = np.concatenate([eu, ev]), np.concatenate([ev, eu]), np.concatenate([ew, ew])
+    order = np.argsort(eu, kind="stable")
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.add.at(row_ptr, eu + 1, 1)
+    return np.cumsum(row_ptr), ev[order].astype(np.int32), ew[order]

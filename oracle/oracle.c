@@ -21,6 +21,11 @@
  *   oracle_label_correcting  the paper's CUDA method (Algorithms 3 and 4) as
  *                          synchronous sweeps over the changed vertices:
  *                          dist, the number of sweeps and the rows relaxed.
+ *   oracle_dijkstra_csr, oracle_certificate_csr, oracle_closed_form_pred_csr
+ *                          the same on a graph stored as adjacency lists
+ *                          (CSR): G[u][v] is the smallest weight of the edges
+ *                          u -> v, self-loops and weights outside
+ *                          [0, INT32_MAX) play no part.
  * All arithmetic on path lengths is exact (int64).
  */
 #include <stdint.h>
@@ -402,5 +407,136 @@ int oracle_hops(const int32_t* pred, const int32_t* dist, int32_t n, int32_t* ho
         while (pred[x] >= 0 && h <= n) { x = pred[x]; ++h; }
         hops[v] = h;
     }
+    return 0;
+}
+
+/* ---------------- graphs stored as adjacency lists (CSR) ---------------- */
+
+/* Edge e of row u (row_ptr[u] <= e < row_ptr[u+1]) is u -> col[e] of weight w[e]. */
+static int or_csr_edge_ok(int32_t u, int32_t v, int32_t w, int32_t n)
+{
+    return v >= 0 && v < n && v != u && w >= 0 && w != OR_INF;
+}
+
+/*
+ * Algorithm 1 (Section III-A) with the relaxation of row u running over u's
+ * edge list instead of a matrix row: identical argmin, strict '<' and int64
+ * sums.  Several edges u -> v are relaxed in list order; the strict '<' makes
+ * the smallest weight win, as G[u][v] = that weight would.
+ * Returns the rows (edge lists) relaxed, or -1 on bad arguments.
+ */
+int64_t oracle_dijkstra_csr(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n,
+                            int32_t src, int32_t* dist, int32_t* pred)
+{
+    if (!row_ptr || !dist || !pred || n < 1 || src < 0 || src >= n) return -1;
+    unsigned char* vis = (unsigned char*)calloc((size_t)n, 1);
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!vis || !d) { free(vis); free(d); return -1; }
+    for (int32_t i = 0; i < n; ++i) { d[i] = OR_INF; pred[i] = -1; }
+    d[src] = 0;
+    int64_t relaxed = 0;
+    for (int32_t it = 0; it < n; ++it) {
+        int32_t u = -1;
+        int64_t best = OR_INF;
+        for (int32_t i = 0; i < n; ++i)
+            if (!vis[i] && d[i] < best) { best = d[i]; u = i; }
+        if (u < 0) break;  /* every unvisited dist is infinite */
+        vis[u] = 1;
+        ++relaxed;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col[e], wt = w[e];
+            if (!or_csr_edge_ok(u, v, wt, n) || vis[v]) continue;
+            const int64_t c = d[u] + wt;
+            if (c < d[v]) { d[v] = c; pred[v] = u; }
+        }
+    }
+    for (int32_t i = 0; i < n; ++i) dist[i] = d[i] >= OR_INF ? OR_INF : (int32_t)d[i];
+    free(vis);
+    free(d);
+    return relaxed;
+}
+
+/*
+ * The shortest-path certificate of (dist, pred) over edge lists; same codes as
+ * oracle_certificate (1 source, 2 infeasible edge, 3 pred edge not tight,
+ * 4 unreachable vertex with a pred, 5 pred chain not reaching the source).
+ * O(n + m).
+ */
+int oracle_certificate_csr(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n,
+                           int32_t src, const int32_t* dist, const int32_t* pred, int64_t* where)
+{
+    if (!row_ptr || !dist || !pred || n < 1 || src < 0 || src >= n) return -1;
+    if (where) *where = -1;
+    if (dist[src] != 0 || pred[src] != -1) { if (where) *where = src; return 1; }
+    /* smallest weight of the edge pred[v] -> v, to check tightness */
+    int64_t* wp = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!wp) return -1;
+    for (int32_t v = 0; v < n; ++v) wp[v] = OR_INF;
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col[e], wt = w[e];
+            if (!or_csr_edge_ok(u, v, wt, n)) continue;
+            if (dist[u] != OR_INF && (int64_t)dist[u] + wt < (int64_t)dist[v]) {
+                free(wp);
+                if (where) *where = v;
+                return 2;
+            }
+            if (pred[v] == u && wt < wp[v]) wp[v] = wt;
+        }
+    for (int32_t v = 0; v < n; ++v) {
+        if (v == src) continue;
+        if (dist[v] == OR_INF) {
+            if (pred[v] != -1) { free(wp); if (where) *where = v; return 4; }
+            continue;
+        }
+        const int32_t p = pred[v];
+        if (p < 0 || p >= n || p == v || dist[p] == OR_INF || wp[v] == OR_INF ||
+            (int64_t)dist[p] + wp[v] != (int64_t)dist[v]) {
+            free(wp);
+            if (where) *where = v;
+            return 3;
+        }
+    }
+    free(wp);
+    unsigned char* cl = (unsigned char*)calloc((size_t)n, 1);
+    int32_t* stack = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!cl || !stack) { free(cl); free(stack); return -1; }
+    cl[src] = 2;
+    for (int32_t v = 0; v < n; ++v) {
+        if (dist[v] == OR_INF || cl[v] == 2) continue;
+        int32_t sp = 0, x = v;
+        while (cl[x] == 0) { cl[x] = 1; stack[sp++] = x; x = pred[x]; }
+        if (cl[x] == 1) { free(cl); free(stack); if (where) *where = v; return 5; }
+        while (sp) cl[stack[--sp]] = 2;
+    }
+    free(cl);
+    free(stack);
+    return 0;
+}
+
+/*
+ * pred[v] = the u != v of smallest (dist[u], u) with an edge u -> v such that
+ * dist[u] + weight == dist[v] (-1 if none), over edge lists: Algorithm 1's pred
+ * whenever no such tight edge has weight 0 (see oracle_closed_form_pred).
+ */
+int oracle_closed_form_pred_csr(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n,
+                                const int32_t* dist, int32_t* pred)
+{
+    if (!row_ptr || !dist || !pred || n < 1) return -1;
+    uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    if (!key) return -1;
+    for (int32_t v = 0; v < n; ++v) key[v] = ~0ULL;
+    for (int32_t u = 0; u < n; ++u) {
+        if (dist[u] == OR_INF) continue;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col[e], wt = w[e];
+            if (!or_csr_edge_ok(u, v, wt, n)) continue;
+            if ((int64_t)dist[u] + wt != (int64_t)dist[v]) continue;
+            const uint64_t k = ((uint64_t)(uint32_t)dist[u] << 32) | (uint32_t)u;
+            if (k < key[v]) key[v] = k;
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) pred[v] = key[v] == ~0ULL ? -1 : (int32_t)(key[v] & 0xffffffffu);
+    free(key);
     return 0;
 }
