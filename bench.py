@@ -126,6 +126,35 @@ def bench_many_levels(sp, torch, gen):
     return out
 
 
+def bench_sparse(sp, torch, gen):
+    """The paper's sparse family (m = 3n undirected edges, weights in [1, 1000], source 0)
+    as adjacency lists: device conversion of the edge list, the CSR solve, and for
+    n <= 40000 the same graph as an n x n matrix (Dijkstra rounds and label-correcting)."""
+    out = []
+    _, specs = gen.workload_sparse()
+    for s in specs:
+        eu, ev, ew = (torch.from_numpy(a).cuda() for a in gen.sparse_edges(s.n, s.m, s.lo, s.hi, s.seed))
+        conv_ms = median_launch_ms(torch, lambda: sp.csr_from_edges(eu, ev, ew, s.n, s.directed), reps=3)
+        rp, col, w, _ = sp.csr_from_edges(eu, ev, ew, s.n, s.directed)
+        ms = median_launch_ms(torch, lambda: sp.csr_solve(rp, col, w, 0))
+        _, stats = sp.sssp_last_status()
+        row = {"n": s.n, "m": s.m, "lists_entries": int(col.numel()), "convert_ms": round(conv_ms, 3),
+               "csr": {"ms_per_solve": round(ms, 3), "sweeps": stats[0], "edge_lists_relaxed": stats[1],
+                       "edges_per_s": col.numel() / (ms * 1e-3)}}
+        if s.n <= 40000:
+            W = torch.empty((s.n, s.n), dtype=torch.int32, device="cuda")
+            sp.sssp_edges_to_dense(eu, ev, ew, s.n, W, directed=s.directed)
+            for name, flags in (("dense_dijkstra", 0), ("dense_label_correcting", sp.SSSP_FLAG_LABEL_CORRECTING)):
+                r = timed_solves(sp, torch, W, 0, 3, 1, flags=flags)
+                row[name] = {"ms_per_solve": round(r["ms_per_step"], 3), "rounds": r["stats"][0],
+                             "rows_streamed": r["stats"][1]}
+            del W
+        out.append(row)
+        del eu, ev, ew, rp, col, w
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(sp, torch, gen):
     """256 sources on one n=8192 graph plus 64 graphs: one-shot launch, autotuned plans
     (int32 and exact compact copies, replayed as a hipGraph) and one solve per launch."""
@@ -401,6 +430,10 @@ def main():
         # ---- sparse graphs with wide weights: Dijkstra rounds vs label-correcting ----
         extra["many_levels"] = bench_many_levels(sp, torch, gen)
         torch.cuda.empty_cache()
+
+        # ---- the sparse family (m = 3n) as adjacency lists ------------------------
+        print("[bench] sparse graphs as adjacency lists", file=sys.stderr, flush=True)
+        extra["sparse_m3n"] = bench_sparse(sp, torch, gen)
 
         # ---- n = 1024, p = 0.1: latency of one solve ------------------------------
         g1 = gen.workload_single_small().graphs[0]

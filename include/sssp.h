@@ -55,6 +55,8 @@ extern "C" {
 #define SSSP_STATUS_NEG_WEIGHT 2      /* a negative weight was seen: precondition violated */
 #define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps, or sent a
                                          label-correcting solve back to the Dijkstra rounds (informational) */
+#define SSSP_STATUS_PRED_TIES 8       /* sssp_csr_solve, n > 65536, tight zero-weight edges: dist exact, pred a
+                                         valid shortest-path tree but not necessarily Algorithm 1's */
 
 /* flags for sssp_dense_solve_ex / batched calls */
 #define SSSP_FLAG_LITERAL 1u  /* settle one vertex per round: Algorithm 1 exactly as printed */
@@ -228,6 +230,44 @@ int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w,
 
 /* Largest n the one-workgroup kernel accepts. */
 int32_t sssp_single_max_n(void);
+
+/* ------------------------------------------------------------------------
+ * Graphs stored as adjacency lists (CSR), for sparse graphs (the paper's m = 3n
+ * family, Section IV-A) whose n x n matrix would waste memory (Section VI).
+ * Row u lists edges u -> col[e] with weight w[e] for row_ptr[u] <= e <
+ * row_ptr[u+1] (row_ptr: n + 1 int64; col, w: int32; device pointers).  The
+ * graph means what the matrix built from the same edges means: G[u][v] is the
+ * smallest weight of the edges u -> v; self-loops and weights outside
+ * [0, INT32_MAX) play no part.
+ * ------------------------------------------------------------------------ */
+
+/* Edge list (eu, ev, ew: m device int32 each) -> CSR on the device: both
+ * orientations of each edge unless `directed`; self-loops dropped; edges with an
+ * endpoint outside [0, n) or a weight outside [0, INT32_MAX) skipped and counted
+ * in *bad_edges.  col and w must hold (directed ? m : 2m) entries; *m_out gets
+ * the number used (row_ptr[n]).  Each row is sorted by (head, weight).
+ * Synchronous (returns after the conversion). */
+int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, int64_t m, int32_t n,
+                      int32_t directed, int64_t* row_ptr, int32_t* col, int32_t* w, int64_t* m_out,
+                      int64_t* bad_edges, void* stream);
+
+/* Single-source solve on a CSR graph: dist and pred as Algorithm 1 computes them
+ * on the equivalent matrix (Section III-A).  The label-correcting method over
+ * edges (see SSSP_FLAG_LABEL_CORRECTING) on a persistent cooperative grid, the
+ * closed-form pred, and for tight zero-weight edges Algorithm 1 run literally by
+ * one workgroup (n <= 65536; above, SSSP_STATUS_PRED_TIES).  tuning->workgroups
+ * (may be NULL) sets the grid (default about n / 256; never above 1024 nor the
+ * co-resident count).  Stats: ROUNDS = sweeps, SETTLED = edge lists
+ * relaxed (the sweep count may differ between runs; dist and pred do not).
+ * Allocates stream-ordered scratch of about 32 n bytes.  Asynchronous. */
+int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n, int32_t src,
+                   int32_t* dist, int32_t* pred, const sssp_tuning* tuning, void* stream);
+
+/* The grid sssp_csr_solve would launch for n vertices on the stream's device:
+ * *workgroups, and (each may be NULL) the co-resident workgroups per compute unit
+ * and the compute units that bound it. */
+int sssp_csr_grid(int32_t n, const sssp_tuning* tuning, void* stream, int32_t* workgroups, int32_t* per_cu,
+                  int32_t* cus);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of (graph, source) queries on a persistent

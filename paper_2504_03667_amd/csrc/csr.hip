@@ -1,0 +1,576 @@
+// Graphs stored as adjacency lists (CSR): the paper's sparse family (m = 3n
+// edges, Section IV-A) without the n x n matrix whose memory the paper names as
+// its weakness (Section VI).  G[u][v] is the smallest weight of the edges
+// u -> v; self-loops and weights outside [0, INT32_MAX) play no part, exactly as
+// for a matrix built from the same edge list.
+//
+// Such graphs have many distinct distances and few edges, so the solve uses the
+// label-correcting method (the paper's CUDA design, Algorithms 3 and 4, made
+// deterministic in its results) over edges:
+//   * a persistent cooperative grid; sweep k relaxes the edge lists of the
+//     vertices whose dist dropped in sweep k-1 (the first frontier is the
+//     source) with an agent-scope atomic minimum on the head's running dist;
+//     the first lowering of a vertex in a sweep appends it to the next
+//     frontier (three frontier lists rotate, so a list is cleared one sweep
+//     before it is filled again); a sweep reads each tail's current dist, so
+//     the sweep count can vary from run to run, the distances cannot;
+//   * every word shared between workgroups is read and written with
+//     agent-scope atomics (coherent across XCDs), so the barrier between
+//     sweeps needs no cache writeback or invalidate;
+//   * once no dist changes, one pass over all edges sets pred[v] to the tail u
+//     of smallest (dist[u], u) among tight edges u -> v, u != v: Algorithm 1's
+//     pred unless a tight edge has weight 0.  Then, for n <= 65536, one
+//     workgroup runs Algorithm 1 literally over the lists (exact pred); for
+//     larger n, further sweeps count the zero-weight edges after the last
+//     positive one on a shortest path into each vertex, pred takes a tight edge
+//     that lowers (dist, that count), which gives a shortest-path tree, and
+//     status bit SSSP_STATUS_PRED_TIES reports that it may differ from
+//     Algorithm 1's.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+
+#include "engine.h"
+#include "sssp.h"
+#include "sssp_internal.h"
+
+namespace sssp {
+int set_error(int code, const char* msg);                                     // api.cpp
+int stream_ctl(hipStream_t stream, Ctl** out, int* cus, long long* clock_khz);  // api.cpp
+
+namespace {
+
+int err(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return set_error(code, buf);
+}
+
+constexpr int kCsrThreads = 256;
+constexpr int32_t kLiteralMaxN = 65536;
+
+// Control words of one CSR solve (device memory, zeroed by k_csr_init).
+struct CsrCtl {
+    uint32_t bar;  // barrier arrivals
+    uint32_t pad0[31];
+    uint32_t gen;  // last completed barrier
+    uint32_t pad1[31];
+    uint32_t count[3];   // frontier list sizes of the distance sweeps
+    uint32_t hcount[3];  // frontier list sizes of the zero-hop sweeps
+    uint32_t zero;       // a tight zero-weight edge was seen
+    uint32_t neg;        // a negative weight was seen
+    uint32_t pad2[24];
+};
+
+__device__ __forceinline__ bool edge_ok(int32_t u, int32_t v, int32_t w, int32_t n) {
+    return v >= 0 && v < n && v != u && w >= 0 && w != (int32_t)kInf;
+}
+
+// ---------------------------------------------------------------------------
+// Edge list -> CSR.
+// ---------------------------------------------------------------------------
+
+// Edges kept: endpoints in [0, n), weight in [0, INT32_MAX), not a self-loop.
+__device__ __forceinline__ bool keep_edge(int32_t u, int32_t v, int32_t w, int32_t n) {
+    return u >= 0 && u < n && v >= 0 && v < n && u != v && w >= 0 && w != (int32_t)kInf;
+}
+
+__global__ void k_csr_degree(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                             const int32_t* __restrict__ ew, int64_t m, int32_t n, int32_t directed,
+                             uint32_t* __restrict__ deg, unsigned long long* __restrict__ bad) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = eu[e], v = ev[e], w = ew[e];
+        const bool self = u == v && u >= 0 && u < n && w >= 0 && w != (int32_t)kInf;
+        if (!keep_edge(u, v, w, n)) {
+            if (!self) atomicAdd(bad, 1ull);  // a valid self-loop is ignored, not an error
+            continue;
+        }
+        atomicAdd(&deg[u], 1u);
+        if (!directed) atomicAdd(&deg[v], 1u);
+    }
+}
+
+// row_ptr[0] = 0, row_ptr[i + 1] = row_ptr[i] + deg[i]: one workgroup, chunk by chunk.
+__global__ __launch_bounds__(1024) void k_csr_scan(const uint32_t* __restrict__ deg, int32_t n,
+                                                   int64_t* __restrict__ row_ptr) {
+    __shared__ unsigned long long wsum[16];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        row_ptr[0] = 0;
+    }
+    __syncthreads();
+    for (int32_t base = 0; base < n; base += 1024) {
+        const int32_t i = base + (int32_t)threadIdx.x;
+        unsigned long long x = i < n ? deg[i] : 0ull;
+        // inclusive scan within the wave
+        const int lane = threadIdx.x & 63;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, (unsigned)o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[threadIdx.x >> 6] = x;
+        __syncthreads();
+        unsigned long long before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < (int)(threadIdx.x >> 6)) before += wsum[k];
+            total += wsum[k];
+        }
+        if (i < n) row_ptr[i + 1] = (int64_t)(carry + before + x);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void k_csr_fill(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                           const int32_t* __restrict__ ew, int64_t m, int32_t n, int32_t directed,
+                           const int64_t* __restrict__ row_ptr, uint32_t* __restrict__ cursor,
+                           int32_t* __restrict__ col, int32_t* __restrict__ w) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = eu[e], v = ev[e], wt = ew[e];
+        if (!keep_edge(u, v, wt, n)) continue;
+        int64_t p = row_ptr[u] + atomicAdd(&cursor[u], 1u);
+        col[p] = v;
+        w[p] = wt;
+        if (!directed) {
+            p = row_ptr[v] + atomicAdd(&cursor[v], 1u);
+            col[p] = u;
+            w[p] = wt;
+        }
+    }
+}
+
+// Sort each row by (head, weight) so that the lists do not depend on the order
+// the atomics above took (one thread per row: the rows of the sparse graphs
+// this serves are short).
+__global__ void k_csr_sort_rows(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ col,
+                                int32_t* __restrict__ w) {
+    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const int64_t a = row_ptr[u], b = row_ptr[u + 1];
+        for (int64_t i = a + 1; i < b; ++i) {
+            const int32_t cv = col[i], cw = w[i];
+            int64_t j = i - 1;
+            while (j >= a && (col[j] > cv || (col[j] == cv && w[j] > cw))) {
+                col[j + 1] = col[j];
+                w[j + 1] = w[j];
+                --j;
+            }
+            col[j + 1] = cv;
+            w[j + 1] = cw;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Solve.
+// ---------------------------------------------------------------------------
+
+__global__ void k_csr_init(int32_t n, int32_t src, uint32_t* __restrict__ cand, uint64_t* __restrict__ pkey,
+                           uint32_t* __restrict__ queued, uint32_t* __restrict__ hop, uint32_t* __restrict__ lists,
+                           CsrCtl* __restrict__ cc) {
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = gtid; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        cand[v] = v == src ? 0u : kInf;
+        pkey[v] = kNoKey;
+        queued[v] = 0;
+        hop[v] = kInf;
+    }
+    if (gtid == 0) {
+        lists[0] = (uint32_t)src;
+        cc->bar = 0;
+        cc->gen = 0;
+        for (int i = 0; i < 3; ++i) {
+            cc->count[i] = i == 0 ? 1u : 0u;
+            cc->hcount[i] = 0;
+        }
+        cc->zero = 0;
+        cc->neg = 0;
+    }
+}
+
+// Grid barrier b of nwg workgroups.  Everything shared goes through agent-scope
+// atomics, whose completion each wave waits for before the workgroup barrier,
+// so an arrival counter and a release word suffice.  false: a wait gave up.
+__device__ __forceinline__ bool csr_barrier(CsrCtl* cc, uint32_t b, uint32_t nwg, long long timeout) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (nwg == 1) return true;
+    int late = 0;
+    if (threadIdx.x == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(&cc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == b * nwg - 1) {
+            st_agent(&cc->gen, b);
+        } else {
+            const long long t0 = wall_clock64();
+            unsigned naps = 1;
+            while (ld_agent(&cc->gen) < b) {
+                for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
+                if (naps < 32) naps <<= 1;
+                if (wall_clock64() - t0 > timeout) {
+                    late = 1;
+                    break;
+                }
+            }
+        }
+    }
+    return __syncthreads_or(late) == 0;
+}
+
+// Algorithm 1 over the lists, one workgroup: the exact pred when tight
+// zero-weight edges make the closed form unusable.  cand holds dist, queued
+// the visited flags.
+template <int T>
+__device__ void csr_literal(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ w, int32_t n, int32_t src, uint32_t* __restrict__ cand,
+                            uint32_t* __restrict__ visited, int32_t* __restrict__ pred, Red<T>& red,
+                            unsigned long long& rows) {
+    for (int32_t v = threadIdx.x; v < n; v += T) {
+        cand[v] = v == src ? 0u : kInf;
+        visited[v] = 0;
+        pred[v] = -1;
+    }
+    __syncthreads();
+    for (;;) {
+        uint64_t key = kNoKey;
+        for (int32_t v = threadIdx.x; v < n; v += T)
+            if (!visited[v]) key = umin64(key, make_key(cand[v], (uint32_t)v));
+        uint32_t none = 0;
+        block_min_or<T>(key, none, red);
+        const uint32_t du = (uint32_t)(key >> 32);
+        if (key == kNoKey || du >= kInf) break;
+        const int32_t u = (int32_t)(uint32_t)key;
+        if (threadIdx.x == 0) {
+            visited[u] = 1;
+            ++rows;
+            // the edges of u in list order; strict '<' keeps a repeated pair's smallest weight
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int32_t v = col[e], wt = w[e];
+                if (!edge_ok(u, v, wt, n) || visited[v]) continue;
+                const uint32_t c = du + (uint32_t)wt;
+                if (c < cand[v]) {
+                    cand[v] = c;
+                    pred[v] = u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Frontier sweeps over three rotating lists whose sizes are count[0..2] (count[0]
+// holds the first frontier, the others are zero).  relax(u, push) relaxes the edge
+// list of frontier vertex u and calls push(v) for each head it lowered; the first
+// push of v in a sweep (stamp stamp0 + sweep in queued[v]) appends it to the next
+// frontier, so a list holds each vertex at most once.  The list read in one sweep is
+// cleared in the next and filled in the one after.  Stops at an empty frontier;
+// false if a barrier wait gave up.
+template <class Relax>
+__device__ bool frontier_sweeps(uint32_t* __restrict__ count, uint32_t* __restrict__ lists,
+                                uint32_t* __restrict__ queued, int32_t n, CsrCtl* cc, uint32_t& b, long long timeout,
+                                uint32_t stamp0, unsigned long long& sweeps, unsigned long long& rows, Relax relax) {
+    const uint32_t nwg = gridDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gsz = (int64_t)nwg * blockDim.x;
+    for (uint32_t k = 0;; ++k) {
+        const uint32_t cur = k % 3, nxt = (k + 1) % 3, old = (k + 2) % 3;
+        const uint32_t F = ld_agent(&count[cur]);
+        if (F == 0) return true;
+        ++sweeps;
+        rows += F;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&count[old], 0u);
+        const uint32_t stamp = stamp0 + k + 1;
+        uint32_t* next = lists + (size_t)nxt * n;
+        auto push = [&](int32_t v) {
+            if (__hip_atomic_exchange(&queued[v], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != stamp) {
+                const uint32_t pos = __hip_atomic_fetch_add(&count[nxt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_agent(&next[pos], (uint32_t)v);
+            }
+        };
+        for (int64_t i = gtid; i < F; i += gsz) relax((int32_t)ld_agent(&lists[(size_t)cur * n + i]), push);
+        if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ w, int32_t n, int32_t src,
+                                              int32_t* __restrict__ dist, int32_t* __restrict__ pred,
+                                              uint32_t* __restrict__ cand, uint64_t* __restrict__ pkey,
+                                              uint32_t* __restrict__ queued, uint32_t* __restrict__ hop,
+                                              uint32_t* __restrict__ lists, CsrCtl* __restrict__ cc,
+                                              long long timeout, Ctl* __restrict__ ctl) {
+    __shared__ Red<T> red;
+    const uint32_t nwg = gridDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * T + threadIdx.x;
+    const int64_t gsz = (int64_t)nwg * T;
+    uint32_t b = 0;
+    unsigned long long sweeps = 0, rows = 0;
+    uint32_t neg = 0;
+    // distances: label-correcting sweeps from the source
+    bool ok = frontier_sweeps(cc->count, lists, queued, n, cc, b, timeout, 0u, sweeps, rows,
+                              [&](int32_t u, auto& push) {
+        const uint32_t du = ld_agent(&cand[u]);
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t v = col[e], wt = w[e];
+            if (!edge_ok(u, v, wt, n)) {
+                neg |= wt < 0 ? 1u : 0u;
+                continue;
+            }
+            const uint32_t c = du + (uint32_t)wt;  // both < 2^31: no wrap
+            if (c >= kInf) continue;                // longer than INT32_MAX - 1: not representable
+            if (c < __hip_atomic_fetch_min(&cand[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) push(v);
+        }
+    });
+    uint32_t zero = 0;
+    if (ok) {
+        // pred pass: the tight edge of smallest (dist[u], u) into each vertex
+        for (int64_t u = gtid; u < n; u += gsz) {
+            const uint32_t du = ld_agent(&cand[u]);
+            if (du >= kInf) continue;
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int32_t v = col[e], wt = w[e];
+                if (!edge_ok((int32_t)u, v, wt, n)) continue;
+                const uint32_t dv = ld_agent(&cand[v]);
+                if (dv >= kInf || du + (uint32_t)wt != dv) continue;  // unreachable heads have no pred
+                __hip_atomic_fetch_min(&pkey[v], make_key(du, (uint32_t)u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                zero |= wt == 0 ? 1u : 0u;
+            }
+        }
+        if (zero) __hip_atomic_fetch_or(&cc->zero, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (neg) __hip_atomic_fetch_or(&cc->neg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = csr_barrier(cc, ++b, nwg, timeout);
+    }
+    uint32_t status = ok ? 0u : kStatusTimeout;
+    const uint32_t Z = ok ? ld_agent(&cc->zero) : 0u;
+    if (ok && Z && n <= kLiteralMaxN) {
+        // tight zero-weight edges: Algorithm 1 literally, by workgroup 0 alone
+        if (blockIdx.x != 0) return;
+        csr_literal<T>(row_ptr, col, w, n, src, cand, queued, pred, red, rows);
+        for (int32_t v = threadIdx.x; v < n; v += T) dist[v] = (int32_t)cand[v];
+        status |= kStatusZeroFallback;
+    } else if (ok && Z) {
+        // Tight zero-weight edges on a graph too large for the literal pass: equal
+        // distances can now point at each other, so the pred of smallest
+        // (dist[u], u) may close a cycle.  hop[v] = fewest tight zero-weight edges
+        // after the last positive-weight edge of a shortest path into v (0 for the
+        // source and for heads of tight positive edges); pred then takes a tight
+        // positive edge, or a tight zero-weight edge from hop[v] - 1, of smallest
+        // (dist[u], u): a shortest-path tree, though not always Algorithm 1's.
+        if (gtid == 0 && __hip_atomic_exchange(&hop[src], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            const uint32_t pos = __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st_agent(&lists[pos], (uint32_t)src);
+        }
+        for (int64_t u = gtid; u < n; u += gsz) {
+            st_agent(&pkey[u], kNoKey);
+            const uint32_t du = ld_agent(&cand[u]);
+            if (du >= kInf) continue;
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int32_t v = col[e], wt = w[e];
+                if (wt == 0 || !edge_ok((int32_t)u, v, wt, n) || du + (uint32_t)wt != ld_agent(&cand[v])) continue;
+                if (__hip_atomic_exchange(&hop[v], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    const uint32_t pos =
+                        __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    st_agent(&lists[pos], (uint32_t)v);
+                }
+            }
+        }
+        ok = csr_barrier(cc, ++b, nwg, timeout);
+        unsigned long long hs = 0, hr = 0;
+        if (ok)
+            ok = frontier_sweeps(cc->hcount, lists, queued, n, cc, b, timeout, 0x80000000u, hs, hr,
+                                 [&](int32_t u, auto& push) {
+                const uint32_t du = ld_agent(&cand[u]);
+                const uint32_t c = ld_agent(&hop[u]) + 1u;
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int32_t v = col[e];
+                    if (w[e] != 0 || !edge_ok(u, v, 0, n) || ld_agent(&cand[v]) != du) continue;
+                    if (c < __hip_atomic_fetch_min(&hop[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) push(v);
+                }
+            });
+        if (ok) {
+            for (int64_t u = gtid; u < n; u += gsz) {
+                const uint32_t du = ld_agent(&cand[u]);
+                if (du >= kInf) continue;
+                const uint32_t hu = ld_agent(&hop[u]);
+                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                    const int32_t v = col[e], wt = w[e];
+                    if (!edge_ok((int32_t)u, v, wt, n) || du + (uint32_t)wt != ld_agent(&cand[v])) continue;
+                    if (wt == 0 && hu + 1u != ld_agent(&hop[v])) continue;
+                    __hip_atomic_fetch_min(&pkey[v], make_key(du, (uint32_t)u), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            ok = csr_barrier(cc, ++b, nwg, timeout);
+        }
+        if (ok) {
+            for (int64_t v = gtid; v < n; v += gsz) {
+                const uint32_t d = ld_agent(&cand[v]);
+                const uint64_t kk = ld_agent(&pkey[v]);
+                dist[v] = (int32_t)d;
+                pred[v] = (v == src || d >= kInf || kk == kNoKey) ? -1 : (int32_t)(uint32_t)kk;
+            }
+            status |= SSSP_STATUS_PRED_TIES;
+        } else {
+            status |= kStatusTimeout;
+        }
+    } else if (ok) {
+        for (int64_t v = gtid; v < n; v += gsz) {
+            const uint32_t d = ld_agent(&cand[v]);
+            const uint64_t kk = ld_agent(&pkey[v]);
+            dist[v] = (int32_t)d;
+            pred[v] = (v == src || d >= kInf || kk == kNoKey) ? -1 : (int32_t)(uint32_t)kk;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok && ld_agent(&cc->neg)) status |= kStatusNegWeight;
+        ctl->last[kStatRounds] = sweeps;
+        ctl->last[kStatSettled] = rows;
+        ctl->last[kStatFallbacks] = (status & kStatusZeroFallback) ? 1 : 0;
+        ctl->last[kStatBarriers] = b;
+        ctl->status = status;
+    }
+}
+
+}  // namespace
+
+int csr_occupancy(int* per_cu) {
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), kCsrThreads, 0);
+}
+
+}  // namespace sssp
+
+using namespace sssp;
+
+namespace {
+
+// Workgroups of a CSR solve: about 256 vertices each, at most 1024 and at most
+// the occupancy query times the compute units.  The 1024 cap is measured, not
+// derived: at 2048 workgroups (8 per CU, the query's maximum for this kernel)
+// grid barriers of the n = 10^6 solve waited out their time limit, so not every
+// workgroup was resident, while 1024 on the same graph runs to the end.
+constexpr int kCsrMaxGrid = 1024;
+
+int csr_grid(int32_t n, const sssp_tuning* tuning, int cus, int* nwg, int* per_cu_out) {
+    int per_cu = 0;
+    if (csr_occupancy(&per_cu) != 0 || per_cu < 1) return err(SSSP_EDEVICE, "CSR kernel does not fit a CU");
+    int g = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 255) / 256);
+    *nwg = std::max(1, std::min({g, per_cu * cus, kCsrMaxGrid}));
+    if (per_cu_out) *per_cu_out = per_cu;
+    return SSSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sssp_csr_grid(int32_t n, const sssp_tuning* tuning, void* stream, int32_t* workgroups, int32_t* per_cu,
+                  int32_t* cus) {
+    if (n < 1 || !workgroups) return err(SSSP_EINVAL, "bad arguments (n=%d)", n);
+    Ctl* ctl = nullptr;
+    int c = 0;
+    long long khz = 0;
+    int rc = stream_ctl((hipStream_t)stream, &ctl, &c, &khz);
+    if (rc) return rc;
+    int g = 0, pc = 0;
+    if ((rc = csr_grid(n, tuning, c, &g, &pc))) return rc;
+    *workgroups = g;
+    if (per_cu) *per_cu = pc;
+    if (cus) *cus = c;
+    return SSSP_OK;
+}
+
+int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, int64_t m, int32_t n,
+                      int32_t directed, int64_t* row_ptr, int32_t* col, int32_t* w, int64_t* m_out,
+                      int64_t* bad_edges, void* stream) {
+    if (!row_ptr || n < 1 || m < 0 || (m > 0 && (!eu || !ev || !ew || !col || !w)))
+        return err(SSSP_EINVAL, "bad arguments (n=%d m=%lld)", n, (long long)m);
+    hipStream_t s = (hipStream_t)stream;
+    // scratch: degrees, then cursors (n words each), and the bad-edge counter
+    char* buf = nullptr;
+    const size_t bytes = 2 * sizeof(uint32_t) * (size_t)n + sizeof(unsigned long long);
+    hipError_t e = hipMallocAsync((void**)&buf, bytes, s);
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync: %s", hipGetErrorString(e));
+    uint32_t* deg = reinterpret_cast<uint32_t*>(buf);
+    uint32_t* cursor = deg + n;
+    unsigned long long* bad = reinterpret_cast<unsigned long long*>(cursor + n);
+    e = zero_fill(buf, (bytes + 3) & ~size_t(3), s);
+    const unsigned eb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (m + 255) / 256), 8192);
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (e == hipSuccess && m > 0) {
+        hipLaunchKernelGGL(k_csr_degree, dim3(eb), dim3(256), 0, s, eu, ev, ew, m, n, directed, deg, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(1024), 0, s, deg, n, row_ptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && m > 0) {
+        hipLaunchKernelGGL(k_csr_fill, dim3(eb), dim3(256), 0, s, eu, ev, ew, m, n, directed, row_ptr, cursor, col, w);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && m > 0) {
+        hipLaunchKernelGGL(k_csr_sort_rows, dim3(nb), dim3(256), 0, s, row_ptr, n, col, w);
+        e = hipGetLastError();
+    }
+    int64_t total = 0;
+    unsigned long long nbad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, row_ptr + n, sizeof total, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(buf, s);
+    if (e != hipSuccess) return err(SSSP_EDEVICE, "edge list conversion: %s", hipGetErrorString(e));
+    if (m_out) *m_out = total;
+    if (bad_edges) *bad_edges = (int64_t)nbad;
+    return SSSP_OK;
+}
+
+int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n, int32_t src,
+                   int32_t* dist, int32_t* pred, const sssp_tuning* tuning, void* stream) {
+    if (!row_ptr || !dist || !pred || n < 1) return err(SSSP_EINVAL, "bad arguments (n=%d)", n);
+    if (src < 0 || src >= n) return err(SSSP_EINVAL, "src %d outside [0, %d)", src, n);
+    hipStream_t s = (hipStream_t)stream;
+    Ctl* ctl = nullptr;
+    int cus = 0;
+    long long khz = 100000;
+    int rc = stream_ctl(s, &ctl, &cus, &khz);
+    if (rc) return rc;
+    int nwg = 0;
+    if ((rc = csr_grid(n, tuning, cus, &nwg, nullptr))) return rc;
+    // scratch: pred keys (n x 8 B), running dist, queued stamps, zero hops (n each), 3 frontier lists
+    // (3n), control
+    const size_t words = (size_t)n;
+    const size_t bytes = words * 8 + 3 * words * 4 + 3 * words * 4 + sizeof(CsrCtl) + 256;
+    char* buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&buf, bytes, s);
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+    uint64_t* pkey = reinterpret_cast<uint64_t*>(buf);
+    uint32_t* cand = reinterpret_cast<uint32_t*>(pkey + words);
+    uint32_t* queued = cand + words;
+    uint32_t* hop = queued + words;
+    uint32_t* lists = hop + words;
+    CsrCtl* cc = reinterpret_cast<CsrCtl*>(((uintptr_t)(lists + 3 * words) + 255) & ~(uintptr_t)255);
+    const unsigned ib = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, cand, pkey, queued, hop, lists, cc);
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        long long timeout = khz * 10000;  // 10 s per barrier wait
+        void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &cand, &pkey,
+                        &queued, &hop, &lists, &cc, &timeout, &ctl};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), dim3(nwg),
+                                       dim3(kCsrThreads), args, 0, s);
+    }
+    (void)hipFreeAsync(buf, s);
+    if (e != hipSuccess) return err(SSSP_EDEVICE, "CSR solve launch: %s", hipGetErrorString(e));
+    return SSSP_OK;
+}
+
+}  // extern "C"

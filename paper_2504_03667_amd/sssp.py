@@ -25,6 +25,7 @@ SSSP_EUNSUPPORTED = -7
 SSSP_STATUS_TIMEOUT = 1
 SSSP_STATUS_NEG_WEIGHT = 2
 SSSP_STATUS_ZERO_FALLBACK = 4
+SSSP_STATUS_PRED_TIES = 8
 
 SSSP_FLAG_LITERAL = 1
 SSSP_FLAG_SINGLE = 2
@@ -127,6 +128,11 @@ def lib():
         L.sssp_hops.argtypes = [P, P, I32, P, P]
         L.sssp_paths.argtypes = [P, P, I32, P, I32, P, P, P]
         L.sssp_single_max_n.restype = I32
+        L.sssp_edges_to_csr.argtypes = [P, P, P, I64, I32, I32, P, P, P, ctypes.POINTER(I64),
+                                        ctypes.POINTER(I64), P]
+        L.sssp_csr_solve.argtypes = [P, P, P, I32, I32, P, P, ctypes.POINTER(sssp_tuning), P]
+        L.sssp_csr_grid.argtypes = [I32, ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                    ctypes.POINTER(I32)]
         L.sssp_server_now_ns.restype = I64
         L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
         L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
@@ -360,6 +366,66 @@ def solve(W, src, flags=0, threads=0, workgroups=0, stream=None):
     dist = torch.empty(n, dtype=torch.int32, device=W.device)
     pred = torch.empty(n, dtype=torch.int32, device=W.device)
     sssp_dense_solve_ex(W, W.stride(0), n, src, dist, pred, flags, threads, workgroups, stream)
+    return dist, pred
+
+
+# ---- graphs stored as adjacency lists (CSR) ----
+
+def _ptr_t(t, dtype, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor on the GPU" % (what, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sssp_edges_to_csr(eu, ev, ew, n, directed, row_ptr, col, w, stream=None):
+    """sssp_edges_to_csr: returns (edges stored, edges skipped)."""
+    m = eu.numel()
+    if ev.numel() != m or ew.numel() != m:
+        raise ValueError("eu, ev, ew must have the same length")
+    cap = m if directed else 2 * m
+    if row_ptr.numel() < n + 1 or col.numel() < cap or w.numel() < cap:
+        raise ValueError("row_ptr needs n + 1 entries, col and w %d" % cap)
+    m_out, bad = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().sssp_edges_to_csr(_ptr_t(eu, torch.int32, "eu"), _ptr_t(ev, torch.int32, "ev"),
+                                   _ptr_t(ew, torch.int32, "ew"), m, n, int(bool(directed)),
+                                   _ptr_t(row_ptr, torch.int64, "row_ptr"), _ptr_t(col, torch.int32, "col"),
+                                   _ptr_t(w, torch.int32, "w"), ctypes.byref(m_out), ctypes.byref(bad),
+                                   _stream(stream)))
+    return m_out.value, bad.value
+
+
+def sssp_csr_solve(row_ptr, col, w, n, src, dist, pred, workgroups=0, stream=None):
+    if row_ptr.numel() < n + 1 or dist.numel() < n or pred.numel() < n:
+        raise ValueError("row_ptr needs n + 1 entries, dist and pred n")
+    return _check(lib().sssp_csr_solve(_ptr_t(row_ptr, torch.int64, "row_ptr"), _ptr_t(col, torch.int32, "col"),
+                                       _ptr_t(w, torch.int32, "w"), n, src, _ptr(dist, "dist"),
+                                       _ptr(pred, "pred"), _tuning(0, workgroups), _stream(stream)))
+
+
+def sssp_csr_grid(n, workgroups=0, stream=None):
+    """(workgroups, co-resident workgroups per CU, CUs) of a CSR solve of n vertices."""
+    g, pc, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().sssp_csr_grid(n, _tuning(0, workgroups), _stream(stream), ctypes.byref(g), ctypes.byref(pc),
+                               ctypes.byref(c)))
+    return g.value, pc.value, c.value
+
+
+def csr_from_edges(eu, ev, ew, n, directed=False, stream=None):
+    """Edge list (device int32 tensors) -> (row_ptr, col, w) device tensors, skipped edges."""
+    cap = eu.numel() if directed else 2 * eu.numel()
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=eu.device)
+    col = torch.empty(max(1, cap), dtype=torch.int32, device=eu.device)
+    w = torch.empty(max(1, cap), dtype=torch.int32, device=eu.device)
+    m_out, bad = sssp_edges_to_csr(eu, ev, ew, n, directed, row_ptr, col, w, stream)
+    return row_ptr, col[:max(1, m_out)], w[:max(1, m_out)], bad
+
+
+def csr_solve(row_ptr, col, w, src, workgroups=0, stream=None):
+    """Solve from src on a CSR graph; returns (dist, pred) tensors."""
+    n = row_ptr.numel() - 1
+    dist = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    pred = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    sssp_csr_solve(row_ptr, col, w, n, src, dist, pred, workgroups, stream)
     return dist, pred
 
 
