@@ -138,8 +138,19 @@ def bench_sparse(sp, torch, gen):
         rp, col, w, _ = sp.csr_from_edges(eu, ev, ew, s.n, s.directed)
         ms = median_launch_ms(torch, lambda: sp.csr_solve(rp, col, w, 0))
         _, stats = sp.sssp_last_status()
+        # device time of one solve (scratch allocation, init and solve kernels) from events on its stream
+        dev_ms = []
+        for _ in range(7):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sp.csr_solve(rp, col, w, 0)
+            e1.record()
+            e1.synchronize()
+            dev_ms.append(e0.elapsed_time(e1))
+        dms = percentile(dev_ms, 50)
         row = {"n": s.n, "m": s.m, "lists_entries": int(col.numel()), "convert_ms": round(conv_ms, 3),
-               "csr": {"ms_per_solve": round(ms, 3), "sweeps": stats[0], "edge_lists_relaxed": stats[1],
+               "csr": {"ms_per_solve": round(ms, 3), "device_ms_median": round(dms, 3), "sweeps": stats[0],
+                       "edge_lists_relaxed": stats[1], "us_per_sweep": round(1e3 * dms / max(1, stats[0]), 2),
                        "edges_per_s": col.numel() / (ms * 1e-3)}}
         if s.n <= 40000:
             W = torch.empty((s.n, s.n), dtype=torch.int32, device="cuda")

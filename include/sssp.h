@@ -259,7 +259,7 @@ int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, i
  * (may be NULL) sets the grid (default about n / 256; never above 1024 nor the
  * co-resident count).  Stats: ROUNDS = sweeps, SETTLED = edge lists
  * relaxed (the sweep count may differ between runs; dist and pred do not).
- * Allocates stream-ordered scratch of about 32 n bytes.  Asynchronous. */
+ * Allocates stream-ordered scratch of about 36 n bytes.  Asynchronous. */
 int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n, int32_t src,
                    int32_t* dist, int32_t* pred, const sssp_tuning* tuning, void* stream);
 

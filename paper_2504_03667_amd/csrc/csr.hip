@@ -59,8 +59,8 @@ constexpr int32_t kLiteralMaxN = 65536;
 struct CsrCtl {
     uint32_t bar;  // barrier arrivals
     uint32_t pad0[31];
-    uint32_t gen;  // last completed barrier
-    uint32_t pad1[31];
+    uint64_t gen;  // (last completed barrier << 32) | the value it hands over
+    uint32_t pad1[30];
     uint32_t count[3];   // frontier list sizes of the distance sweeps
     uint32_t hcount[3];  // frontier list sizes of the zero-hop sweeps
     uint32_t zero;       // a tight zero-weight edge was seen
@@ -170,22 +170,29 @@ __global__ void k_csr_sort_rows(const int64_t* __restrict__ row_ptr, int32_t n, 
 
 // ---------------------------------------------------------------------------
 // Solve.
+//
+// Labels: a running value (dist, or the zero-hop count) and the sweep that last
+// lowered it, packed as (value << 32) | sweep into one 64-bit word.  Sweep
+// numbers grow, so an atomic minimum with (c << 32) | k lowers the value
+// exactly when c is smaller (a tie keeps the older word), and the word it
+// returns tells whether sweep k had already lowered it: only the first
+// lowering of a vertex in a sweep appends it to the next frontier.
 // ---------------------------------------------------------------------------
 
-__global__ void k_csr_init(int32_t n, int32_t src, uint32_t* __restrict__ cand, uint64_t* __restrict__ pkey,
-                           uint32_t* __restrict__ queued, uint32_t* __restrict__ hop, uint32_t* __restrict__ lists,
-                           CsrCtl* __restrict__ cc) {
+__device__ __forceinline__ uint32_t label_value(uint64_t x) { return (uint32_t)(x >> 32); }
+
+__global__ void k_csr_init(int32_t n, int32_t src, uint64_t* __restrict__ lab, uint64_t* __restrict__ pkey,
+                           uint64_t* __restrict__ hop, uint32_t* __restrict__ lists, CsrCtl* __restrict__ cc) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = gtid; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        cand[v] = v == src ? 0u : kInf;
+        lab[v] = v == src ? 0ull : (uint64_t)kInf << 32;
         pkey[v] = kNoKey;
-        queued[v] = 0;
-        hop[v] = kInf;
+        hop[v] = (uint64_t)kInf << 32;
     }
     if (gtid == 0) {
         lists[0] = (uint32_t)src;
         cc->bar = 0;
-        cc->gen = 0;
+        cc->gen = 0ull;
         for (int i = 0; i < 3; ++i) {
             cc->count[i] = i == 0 ? 1u : 0u;
             cc->hcount[i] = 0;
@@ -197,36 +204,52 @@ __global__ void k_csr_init(int32_t n, int32_t src, uint32_t* __restrict__ cand, 
 
 // Grid barrier b of nwg workgroups.  Everything shared goes through agent-scope
 // atomics, whose completion each wave waits for before the workgroup barrier,
-// so an arrival counter and a release word suffice.  false: a wait gave up.
-__device__ __forceinline__ bool csr_barrier(CsrCtl* cc, uint32_t b, uint32_t nwg, long long timeout) {
+// so an arrival counter and a release word suffice.  The last workgroup to
+// arrive reads *carry (when given: by then every other workgroup's atomics on
+// it have completed) and hands it to all in the release word, saving each
+// workgroup that read.  false: a wait gave up.
+__device__ __forceinline__ bool csr_barrier(CsrCtl* cc, uint32_t b, uint32_t nwg, long long timeout,
+                                            const uint32_t* carry = nullptr, uint32_t* value = nullptr) {
+    __shared__ uint32_t handed;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (nwg == 1) return true;
     int late = 0;
     if (threadIdx.x == 0) {
-        const uint32_t old = __hip_atomic_fetch_add(&cc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b * nwg - 1) {
-            st_agent(&cc->gen, b);
+        uint32_t val = 0;
+        if (nwg == 1) {
+            if (carry) val = ld_agent(carry);
         } else {
-            const long long t0 = wall_clock64();
-            unsigned naps = 1;
-            while (ld_agent(&cc->gen) < b) {
-                for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
-                if (naps < 32) naps <<= 1;
-                if (wall_clock64() - t0 > timeout) {
-                    late = 1;
-                    break;
+            const uint32_t old = __hip_atomic_fetch_add(&cc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (old == b * nwg - 1) {
+                if (carry) val = ld_agent(carry);
+                st_agent(&cc->gen, ((uint64_t)b << 32) | val);
+            } else {
+                const long long t0 = wall_clock64();
+                unsigned naps = 1;
+                uint64_t g = ld_agent(&cc->gen);
+                while ((uint32_t)(g >> 32) < b) {
+                    for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
+                    if (naps < 8) naps <<= 1;
+                    if (wall_clock64() - t0 > timeout) {
+                        late = 1;
+                        break;
+                    }
+                    g = ld_agent(&cc->gen);
                 }
+                val = (uint32_t)g;
             }
         }
+        handed = val;
     }
-    return __syncthreads_or(late) == 0;
+    const bool ok = __syncthreads_or(late) == 0;
+    if (value) *value = handed;
+    return ok;
 }
 
 // Algorithm 1 over the lists, one workgroup: the exact pred when tight
-// zero-weight edges make the closed form unusable.  cand holds dist, queued
-// the visited flags.
+// zero-weight edges make the closed form unusable.  cand holds dist, visited
+// the settled flags (n words each, workgroup-private).
 template <int T>
 __device__ void csr_literal(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                             const int32_t* __restrict__ w, int32_t n, int32_t src, uint32_t* __restrict__ cand,
@@ -265,37 +288,138 @@ __device__ void csr_literal(const int64_t* __restrict__ row_ptr, const int32_t* 
     }
 }
 
-// Frontier sweeps over three rotating lists whose sizes are count[0..2] (count[0]
-// holds the first frontier, the others are zero).  relax(u, push) relaxes the edge
-// list of frontier vertex u and calls push(v) for each head it lowered; the first
-// push of v in a sweep (stamp stamp0 + sweep in queued[v]) appends it to the next
-// frontier, so a list holds each vertex at most once.  The list read in one sweep is
-// cleared in the next and filled in the one after.  Stops at an empty frontier;
-// false if a barrier wait gave up.
-template <class Relax>
+// Frontier sweeps over three rotating lists whose sizes are count[0..2]; the
+// first frontier (F vertices) is in list 0.  A group of G lanes takes one
+// frontier vertex u and walks its edge list G * B edges per step, every load
+// and atomic of a step in flight together: value(tail(u), u, v, w, c) says
+// whether edge u -> v takes part and gives its candidate c, and an atomic
+// minimum of (c << 32) | sweep on lab[v] lowers v; its first lowering in the
+// sweep appends v to the next frontier, one counter update per wave and step.
+// A list therefore holds a vertex at most once; the list read in one sweep is
+// cleared in the next and filled in the one after.  Small frontiers are bound
+// by latency: 4 lanes share a vertex so that more waves have work.  Large ones
+// are bound by memory operations: a lane walks a whole list, 8 edges per step,
+// and first reads each head, skipping the atomic when the edge cannot lower it.
+constexpr uint32_t kLargeFrontier = 32768;
+
+template <int G, int B, bool Filter, class Tail, class Value>
+__device__ __forceinline__ void sweep_frontier(const uint32_t* __restrict__ list, uint32_t F,
+                                               uint32_t* __restrict__ next, uint32_t* __restrict__ next_count,
+                                               uint64_t* __restrict__ lab, const int64_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col, const int32_t* __restrict__ w,
+                                               uint32_t tag, Tail& tail, Value& value) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sub = lane % G;
+    const int64_t per_wave = kWave / G;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave) * per_wave;
+    for (int64_t i0 = wave * per_wave; i0 < (int64_t)F; i0 += stride) {  // the same trip count in a wave
+        const int64_t i = i0 + lane / G;
+        int32_t u = 0;
+        decltype(tail(0)) tv{};
+        int64_t e = 0, e1 = 0;
+        if (i < (int64_t)F) {
+            u = (int32_t)ld_agent(&list[i]);
+            tv = tail(u);
+            e = row_ptr[u] + sub;
+            e1 = row_ptr[u + 1];
+        }
+        while (__ballot(e < e1)) {
+            int32_t v[B];
+            uint32_t c[B];
+            uint64_t before[B];
+            bool part[B];
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int64_t ej = e + (int64_t)j * G;
+                part[j] = false;
+                v[j] = 0;
+                c[j] = 0;
+                if (ej < e1) {
+                    v[j] = col[ej];
+                    part[j] = value(tv, u, v[j], w[ej], c[j]);
+                }
+            }
+            if (Filter) {
+                uint64_t now[B];
+#pragma unroll
+                for (int j = 0; j < B; ++j) now[j] = part[j] ? ld_agent(&lab[v[j]]) : 0ull;
+#pragma unroll
+                for (int j = 0; j < B; ++j) part[j] = part[j] && c[j] < label_value(now[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                before[j] = part[j] ? __hip_atomic_fetch_min(&lab[v[j]], ((uint64_t)c[j] << 32) | tag, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)
+                                    : 0ull;
+            uint32_t want = 0;
+#pragma unroll
+            for (int j = 0; j < B; ++j)
+                want |= (part[j] && c[j] < label_value(before[j]) && (uint32_t)before[j] != tag ? 1u : 0u) << j;
+            const uint32_t mine = (uint32_t)__popc(want);
+            const uint32_t incl = wave_scan32(mine);
+            const uint32_t total = __shfl(incl, kWave - 1, kWave);
+            if (total) {
+                uint32_t base = 0;
+                if (lane == kWave - 1)
+                    base = __hip_atomic_fetch_add(next_count, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t pos = __shfl(base, kWave - 1, kWave) + incl - mine;
+#pragma unroll
+                for (int j = 0; j < B; ++j)
+                    if (want >> j & 1u) st_agent(&next[pos++], (uint32_t)v[j]);
+            }
+            e += (int64_t)G * B;
+        }
+    }
+}
+
+// The barrier that ends a sweep hands over the next frontier's size.  Stops at
+// an empty frontier; false if a barrier wait gave up.
+template <class Tail, class Value>
 __device__ bool frontier_sweeps(uint32_t* __restrict__ count, uint32_t* __restrict__ lists,
-                                uint32_t* __restrict__ queued, int32_t n, CsrCtl* cc, uint32_t& b, long long timeout,
-                                uint32_t stamp0, unsigned long long& sweeps, unsigned long long& rows, Relax relax) {
+                                uint64_t* __restrict__ lab, const int64_t* __restrict__ row_ptr,
+                                const int32_t* __restrict__ col, const int32_t* __restrict__ w, int32_t n, CsrCtl* cc,
+                                uint32_t& b, long long timeout, uint32_t F, unsigned long long& sweeps,
+                                unsigned long long& rows, Tail tail, Value value) {
     const uint32_t nwg = gridDim.x;
-    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t gsz = (int64_t)nwg * blockDim.x;
-    for (uint32_t k = 0;; ++k) {
+    for (uint32_t k = 0; F != 0; ++k) {
         const uint32_t cur = k % 3, nxt = (k + 1) % 3, old = (k + 2) % 3;
-        const uint32_t F = ld_agent(&count[cur]);
-        if (F == 0) return true;
         ++sweeps;
         rows += F;
         if (blockIdx.x == 0 && threadIdx.x == 0) st_agent(&count[old], 0u);
-        const uint32_t stamp = stamp0 + k + 1;
+        const uint32_t tag = k + 1;
+        const uint32_t* list = lists + (size_t)cur * n;
         uint32_t* next = lists + (size_t)nxt * n;
-        auto push = [&](int32_t v) {
-            if (__hip_atomic_exchange(&queued[v], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != stamp) {
-                const uint32_t pos = __hip_atomic_fetch_add(&count[nxt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_agent(&next[pos], (uint32_t)v);
+        if (F >= kLargeFrontier)
+            sweep_frontier<1, 8, true>(list, F, next, &count[nxt], lab, row_ptr, col, w, tag, tail, value);
+        else
+            sweep_frontier<4, 2, false>(list, F, next, &count[nxt], lab, row_ptr, col, w, tag, tail, value);
+        if (!csr_barrier(cc, ++b, nwg, timeout, &count[nxt], &F)) return false;
+    }
+    return true;
+}
+
+// Calls f(v[], w[], ok[]) for the edges of u, kBatch at a time, after loading
+// them together; ok marks the edges that take part (edge_ok).
+constexpr int kBatch = 4;
+template <class F>
+__device__ __forceinline__ void for_edges(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                          const int32_t* __restrict__ w, int32_t n, int32_t u, F f) {
+    const int64_t e1 = row_ptr[u + 1];
+    for (int64_t e = row_ptr[u]; e < e1; e += kBatch) {
+        int32_t v[kBatch], wt[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            v[j] = 0;
+            wt[j] = -1;
+            if (e + j < e1) {
+                v[j] = col[e + j];
+                wt[j] = w[e + j];
             }
-        };
-        for (int64_t i = gtid; i < F; i += gsz) relax((int32_t)ld_agent(&lists[(size_t)cur * n + i]), push);
-        if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+            ok[j] = e + j < e1 && edge_ok(u, v[j], wt[j], n);
+        }
+        f(v, wt, ok);
     }
 }
 
@@ -303,10 +427,9 @@ template <int T>
 __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                               const int32_t* __restrict__ w, int32_t n, int32_t src,
                                               int32_t* __restrict__ dist, int32_t* __restrict__ pred,
-                                              uint32_t* __restrict__ cand, uint64_t* __restrict__ pkey,
-                                              uint32_t* __restrict__ queued, uint32_t* __restrict__ hop,
-                                              uint32_t* __restrict__ lists, CsrCtl* __restrict__ cc,
-                                              long long timeout, Ctl* __restrict__ ctl) {
+                                              uint64_t* __restrict__ lab, uint64_t* __restrict__ pkey,
+                                              uint64_t* __restrict__ hop, uint32_t* __restrict__ lists,
+                                              CsrCtl* __restrict__ cc, long long timeout, Ctl* __restrict__ ctl) {
     __shared__ Red<T> red;
     const uint32_t nwg = gridDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * T + threadIdx.x;
@@ -314,35 +437,37 @@ __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_pt
     uint32_t b = 0;
     unsigned long long sweeps = 0, rows = 0;
     uint32_t neg = 0;
-    // distances: label-correcting sweeps from the source
-    bool ok = frontier_sweeps(cc->count, lists, queued, n, cc, b, timeout, 0u, sweeps, rows,
-                              [&](int32_t u, auto& push) {
-        const uint32_t du = ld_agent(&cand[u]);
-        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-            const int32_t v = col[e], wt = w[e];
+    // distances: label-correcting sweeps from the source (the first frontier)
+    bool ok = frontier_sweeps(
+        cc->count, lists, lab, row_ptr, col, w, n, cc, b, timeout, 1u, sweeps, rows,
+        [&](int32_t u) { return label_value(ld_agent(&lab[u])); },
+        [&](uint32_t du, int32_t u, int32_t v, int32_t wt, uint32_t& c) {
             if (!edge_ok(u, v, wt, n)) {
                 neg |= wt < 0 ? 1u : 0u;
-                continue;
+                return false;
             }
-            const uint32_t c = du + (uint32_t)wt;  // both < 2^31: no wrap
-            if (c >= kInf) continue;                // longer than INT32_MAX - 1: not representable
-            if (c < __hip_atomic_fetch_min(&cand[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) push(v);
-        }
-    });
+            c = du + (uint32_t)wt;  // both < 2^31: no wrap
+            return c < kInf;        // longer than INT32_MAX - 1: not representable
+        });
     uint32_t zero = 0;
     if (ok) {
         // pred pass: the tight edge of smallest (dist[u], u) into each vertex
         for (int64_t u = gtid; u < n; u += gsz) {
-            const uint32_t du = ld_agent(&cand[u]);
+            const uint32_t du = label_value(ld_agent(&lab[u]));
             if (du >= kInf) continue;
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int32_t v = col[e], wt = w[e];
-                if (!edge_ok((int32_t)u, v, wt, n)) continue;
-                const uint32_t dv = ld_agent(&cand[v]);
-                if (dv >= kInf || du + (uint32_t)wt != dv) continue;  // unreachable heads have no pred
-                __hip_atomic_fetch_min(&pkey[v], make_key(du, (uint32_t)u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                zero |= wt == 0 ? 1u : 0u;
-            }
+            for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+                uint32_t dv[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) dv[j] = eok[j] ? label_value(ld_agent(&lab[v[j]])) : kInf;
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    // unreachable heads have no pred
+                    if (dv[j] >= kInf || du + (uint32_t)wt[j] != dv[j]) continue;
+                    __hip_atomic_fetch_min(&pkey[v[j]], make_key(du, (uint32_t)u), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    zero |= wt[j] == 0 ? 1u : 0u;
+                }
+            });
         }
         if (zero) __hip_atomic_fetch_or(&cc->zero, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (neg) __hip_atomic_fetch_or(&cc->neg, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -351,9 +476,11 @@ __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_pt
     uint32_t status = ok ? 0u : kStatusTimeout;
     const uint32_t Z = ok ? ld_agent(&cc->zero) : 0u;
     if (ok && Z && n <= kLiteralMaxN) {
-        // tight zero-weight edges: Algorithm 1 literally, by workgroup 0 alone
+        // tight zero-weight edges: Algorithm 1 literally, by workgroup 0 alone, in
+        // the memory of the hop labels (unused on this path)
         if (blockIdx.x != 0) return;
-        csr_literal<T>(row_ptr, col, w, n, src, cand, queued, pred, red, rows);
+        uint32_t* cand = reinterpret_cast<uint32_t*>(hop);
+        csr_literal<T>(row_ptr, col, w, n, src, cand, cand + n, pred, red, rows);
         for (int32_t v = threadIdx.x; v < n; v += T) dist[v] = (int32_t)cand[v];
         status |= kStatusZeroFallback;
     } else if (ok && Z) {
@@ -364,55 +491,67 @@ __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_pt
         // source and for heads of tight positive edges); pred then takes a tight
         // positive edge, or a tight zero-weight edge from hop[v] - 1, of smallest
         // (dist[u], u): a shortest-path tree, though not always Algorithm 1's.
-        if (gtid == 0 && __hip_atomic_exchange(&hop[src], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            const uint32_t pos = __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            st_agent(&lists[pos], (uint32_t)src);
-        }
+        auto seed = [&](int32_t v) {  // hop[v] = 0; the first to set it appends v
+            if (label_value(__hip_atomic_fetch_min(&hop[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u) {
+                const uint32_t pos =
+                    __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_agent(&lists[pos], (uint32_t)v);
+            }
+        };
+        if (gtid == 0) seed(src);
         for (int64_t u = gtid; u < n; u += gsz) {
             st_agent(&pkey[u], kNoKey);
-            const uint32_t du = ld_agent(&cand[u]);
+            const uint32_t du = label_value(ld_agent(&lab[u]));
             if (du >= kInf) continue;
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int32_t v = col[e], wt = w[e];
-                if (wt == 0 || !edge_ok((int32_t)u, v, wt, n) || du + (uint32_t)wt != ld_agent(&cand[v])) continue;
-                if (__hip_atomic_exchange(&hop[v], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    const uint32_t pos =
-                        __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    st_agent(&lists[pos], (uint32_t)v);
-                }
-            }
+            for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+                uint32_t dv[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    dv[j] = (eok[j] && wt[j] != 0) ? label_value(ld_agent(&lab[v[j]])) : kInf;
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    if (dv[j] < kInf && du + (uint32_t)wt[j] == dv[j]) seed(v[j]);
+            });
         }
-        ok = csr_barrier(cc, ++b, nwg, timeout);
+        uint32_t F0 = 0;
+        ok = csr_barrier(cc, ++b, nwg, timeout, &cc->hcount[0], &F0);
         unsigned long long hs = 0, hr = 0;
         if (ok)
-            ok = frontier_sweeps(cc->hcount, lists, queued, n, cc, b, timeout, 0x80000000u, hs, hr,
-                                 [&](int32_t u, auto& push) {
-                const uint32_t du = ld_agent(&cand[u]);
-                const uint32_t c = ld_agent(&hop[u]) + 1u;
-                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                    const int32_t v = col[e];
-                    if (w[e] != 0 || !edge_ok(u, v, 0, n) || ld_agent(&cand[v]) != du) continue;
-                    if (c < __hip_atomic_fetch_min(&hop[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) push(v);
-                }
-            });
+            ok = frontier_sweeps(
+                cc->hcount, lists, hop, row_ptr, col, w, n, cc, b, timeout, F0, hs, hr,
+                [&](int32_t u) { return make_key(label_value(ld_agent(&lab[u])), label_value(ld_agent(&hop[u]))); },
+                [&](uint64_t t, int32_t u, int32_t v, int32_t wt, uint32_t& c) {
+                    if (wt != 0 || !edge_ok(u, v, 0, n) || label_value(ld_agent(&lab[v])) != (uint32_t)(t >> 32))
+                        return false;
+                    c = (uint32_t)t + 1u;
+                    return true;
+                });
         if (ok) {
             for (int64_t u = gtid; u < n; u += gsz) {
-                const uint32_t du = ld_agent(&cand[u]);
+                const uint32_t du = label_value(ld_agent(&lab[u]));
                 if (du >= kInf) continue;
-                const uint32_t hu = ld_agent(&hop[u]);
-                for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                    const int32_t v = col[e], wt = w[e];
-                    if (!edge_ok((int32_t)u, v, wt, n) || du + (uint32_t)wt != ld_agent(&cand[v])) continue;
-                    if (wt == 0 && hu + 1u != ld_agent(&hop[v])) continue;
-                    __hip_atomic_fetch_min(&pkey[v], make_key(du, (uint32_t)u), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
+                const uint32_t hu = label_value(ld_agent(&hop[u]));
+                for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+                    uint32_t dv[kBatch], hv[kBatch];
+#pragma unroll
+                    for (int j = 0; j < kBatch; ++j) {
+                        dv[j] = eok[j] ? label_value(ld_agent(&lab[v[j]])) : kInf;
+                        hv[j] = (eok[j] && wt[j] == 0) ? label_value(ld_agent(&hop[v[j]])) : 0u;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kBatch; ++j) {
+                        if (dv[j] >= kInf || du + (uint32_t)wt[j] != dv[j]) continue;
+                        if (wt[j] == 0 && hu + 1u != hv[j]) continue;
+                        __hip_atomic_fetch_min(&pkey[v[j]], make_key(du, (uint32_t)u), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                });
             }
             ok = csr_barrier(cc, ++b, nwg, timeout);
         }
         if (ok) {
             for (int64_t v = gtid; v < n; v += gsz) {
-                const uint32_t d = ld_agent(&cand[v]);
+                const uint32_t d = label_value(ld_agent(&lab[v]));
                 const uint64_t kk = ld_agent(&pkey[v]);
                 dist[v] = (int32_t)d;
                 pred[v] = (v == src || d >= kInf || kk == kNoKey) ? -1 : (int32_t)(uint32_t)kk;
@@ -423,7 +562,7 @@ __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_pt
         }
     } else if (ok) {
         for (int64_t v = gtid; v < n; v += gsz) {
-            const uint32_t d = ld_agent(&cand[v]);
+            const uint32_t d = label_value(ld_agent(&lab[v]));
             const uint64_t kk = ld_agent(&pkey[v]);
             dist[v] = (int32_t)d;
             pred[v] = (v == src || d >= kInf || kk == kNoKey) ? -1 : (int32_t)(uint32_t)kk;
@@ -545,26 +684,24 @@ int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w,
     if (rc) return rc;
     int nwg = 0;
     if ((rc = csr_grid(n, tuning, cus, &nwg, nullptr))) return rc;
-    // scratch: pred keys (n x 8 B), running dist, queued stamps, zero hops (n each), 3 frontier lists
-    // (3n), control
+    // scratch: dist labels, pred keys, hop labels (n x 8 B each), 3 frontier lists (3n words), control
     const size_t words = (size_t)n;
-    const size_t bytes = words * 8 + 3 * words * 4 + 3 * words * 4 + sizeof(CsrCtl) + 256;
+    const size_t bytes = 3 * words * 8 + 3 * words * 4 + sizeof(CsrCtl) + 256;
     char* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, bytes, s);
     if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
-    uint64_t* pkey = reinterpret_cast<uint64_t*>(buf);
-    uint32_t* cand = reinterpret_cast<uint32_t*>(pkey + words);
-    uint32_t* queued = cand + words;
-    uint32_t* hop = queued + words;
-    uint32_t* lists = hop + words;
+    uint64_t* lab = reinterpret_cast<uint64_t*>(buf);
+    uint64_t* pkey = lab + words;
+    uint64_t* hop = pkey + words;
+    uint32_t* lists = reinterpret_cast<uint32_t*>(hop + words);
     CsrCtl* cc = reinterpret_cast<CsrCtl*>(((uintptr_t)(lists + 3 * words) + 255) & ~(uintptr_t)255);
     const unsigned ib = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, cand, pkey, queued, hop, lists, cc);
+    hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, lab, pkey, hop, lists, cc);
     e = hipGetLastError();
     if (e == hipSuccess) {
         long long timeout = khz * 10000;  // 10 s per barrier wait
-        void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &cand, &pkey,
-                        &queued, &hop, &lists, &cc, &timeout, &ctl};
+        void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &lab, &pkey,
+                        &hop, &lists, &cc, &timeout, &ctl};
         e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), dim3(nwg),
                                        dim3(kCsrThreads), args, 0, s);
     }
