@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+SECTIONS = ("medium", "many_levels", "sparse", "small", "batched", "served")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +42,8 @@ def parse():
                     help="queries of the served trace (Poisson arrivals at 2000/s)")
     ap.add_argument("--plain-queries", type=int, default=2000,
                     help="queries of the trace replayed one solve per launch for comparison")
+    ap.add_argument("--section", choices=SECTIONS,
+                    help="run only this part of the benchmark and print its figures (no headline line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 4 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -103,6 +108,48 @@ def median_launch_ms(torch, fn, reps=7):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     return sorted(ts)[len(ts) // 2] * 1e3
+
+
+def bench_medium(sp, torch, gen):
+    """n=16384, p=0.01 (1 GiB), undirected and directed, sources 0/7/12345: the whole-GPU solve
+    (and the label-correcting method beside it)."""
+    wl2 = gen.workload_single_medium()
+    med = []
+    for gi, g in enumerate(wl2.graphs):
+        Wm = gen.dense_device(g)
+        for g2, src in wl2.instances:
+            if g2 != gi:
+                continue
+            rr = timed_solves(sp, torch, Wm, src, 10, 2)
+            kms = percentile(rr["kernel_ms"], 50)
+            gbps = (4.0 * g.n * rr["stats"][1] + 8.0 * g.n) / (kms * 1e-3) / 1e9
+            lc = timed_solves(sp, torch, Wm, src, 10, 2, flags=sp.SSSP_FLAG_LABEL_CORRECTING)
+            med.append({"directed": g.directed, "src": src, "ms_per_solve": round(rr["ms_per_step"], 4),
+                        "kernel_ms_median": round(kms, 4), "rows_relaxed": rr["stats"][1],
+                        "rounds": rr["stats"][0],
+                        "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3),
+                        "algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4),
+                        "label_correcting": {"ms_per_solve": round(lc["ms_per_step"], 4),
+                                             "sweeps": lc["stats"][0], "rows_streamed": lc["stats"][1]}})
+            del lc
+        del Wm
+    return med
+
+
+def bench_small(sp, torch, gen):
+    """n=1024, p=0.1: latency of one solve, one workgroup and whole GPU."""
+    g1 = gen.workload_single_small().graphs[0]
+    W1 = gen.dense_device(g1)
+    c1 = {}
+    for mode, flags, reps in (("single_workgroup", 0, 1000), ("whole_gpu", sp.SSSP_FLAG_GRID, 200)):
+        rr = timed_solves(sp, torch, W1, 0, reps, 10, flags=flags)
+        med_us = 1e3 * percentile(rr["kernel_ms"], 50)
+        c1[mode] = {"reps": reps, "median_us": round(med_us, 2),
+                    "p99_us": round(1e3 * percentile(rr["kernel_ms"], 99), 2),
+                    "rounds": rr["stats"][0], "rows_relaxed": rr["stats"][1],
+                    "entries_per_s": g1.n * rr["stats"][1] / (med_us * 1e-6)}
+    del W1
+    return c1
 
 
 def bench_many_levels(sp, torch, gen):
@@ -366,6 +413,12 @@ def main():
     import paper_2504_03667_amd as sp
 
     sp.lib()
+    if args.section:
+        run = {"medium": bench_medium, "many_levels": bench_many_levels, "sparse": bench_sparse,
+               "small": bench_small, "batched": bench_batched,
+               "served": lambda sp, torch, gen: bench_served(sp, torch, gen, args)}[args.section]
+        print(json.dumps({"section": args.section, args.section: run(sp, torch, gen)}))
+        return 0
     if args.copy_calibration:
         # a copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
         a = torch.empty(1 << 30, dtype=torch.int32, device="cuda")
@@ -414,28 +467,7 @@ def main():
 
     extra = {}
     if not args.only_large:
-        # ---- n = 16384, p = 0.01: undirected and directed, three sources ----------
-        wl2 = gen.workload_single_medium()
-        med = []
-        for gi, g in enumerate(wl2.graphs):
-            Wm = gen.dense_device(g)
-            for g2, src in wl2.instances:
-                if g2 != gi:
-                    continue
-                rr = timed_solves(sp, torch, Wm, src, 10, 2)
-                kms = percentile(rr["kernel_ms"], 50)
-                gbps = (4.0 * g.n * rr["stats"][1] + 8.0 * g.n) / (kms * 1e-3) / 1e9
-                lc = timed_solves(sp, torch, Wm, src, 10, 2, flags=sp.SSSP_FLAG_LABEL_CORRECTING)
-                med.append({"directed": g.directed, "src": src, "ms_per_solve": round(rr["ms_per_step"], 4),
-                            "kernel_ms_median": round(kms, 4), "rows_relaxed": rr["stats"][1],
-                            "rounds": rr["stats"][0],
-                            "entries_per_s": g.n * rr["stats"][1] / (rr["ms_per_step"] * 1e-3),
-                            "algorithmic_GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBS, 4),
-                            "label_correcting": {"ms_per_solve": round(lc["ms_per_step"], 4),
-                                                 "sweeps": lc["stats"][0], "rows_streamed": lc["stats"][1]}})
-                del lc
-            del Wm
-        extra["n16384"] = med
+        extra["n16384"] = bench_medium(sp, torch, gen)
         torch.cuda.empty_cache()
 
         # ---- sparse graphs with wide weights: Dijkstra rounds vs label-correcting ----
@@ -446,19 +478,7 @@ def main():
         print("[bench] sparse graphs as adjacency lists", file=sys.stderr, flush=True)
         extra["sparse_m3n"] = bench_sparse(sp, torch, gen)
 
-        # ---- n = 1024, p = 0.1: latency of one solve ------------------------------
-        g1 = gen.workload_single_small().graphs[0]
-        W1 = gen.dense_device(g1)
-        c1 = {}
-        for mode, flags, reps in (("single_workgroup", 0, 1000), ("whole_gpu", sp.SSSP_FLAG_GRID, 200)):
-            rr = timed_solves(sp, torch, W1, 0, reps, 10, flags=flags)
-            med_us = 1e3 * percentile(rr["kernel_ms"], 50)
-            c1[mode] = {"reps": reps, "median_us": round(med_us, 2),
-                        "p99_us": round(1e3 * percentile(rr["kernel_ms"], 99), 2),
-                        "rounds": rr["stats"][0], "rows_relaxed": rr["stats"][1],
-                        "entries_per_s": g1.n * rr["stats"][1] / (med_us * 1e-6)}
-        extra["n1024"] = c1
-        del W1
+        extra["n1024"] = bench_small(sp, torch, gen)
 
         # ---- batched: 320 instances in one launch vs one solve per launch ---------
         extra["batched"] = bench_batched(sp, torch, gen)

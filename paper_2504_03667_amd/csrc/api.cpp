@@ -238,6 +238,15 @@ const char* last_error_text() { return t_err.c_str(); }
 
 // Control block of (current device, stream), marked as used by a launch that
 // the caller is about to enqueue; its stats are what sssp_last_status reports.
+// Launch mode and barrier wait limit of the other persistent grids (the CSR
+// solve), from the same environment settings as the dense whole-GPU solve.
+bool grid_launch_is_plain() { return plain_grid_launch(); }
+long long grid_barrier_ticks(long long clock_khz) {
+    DeviceInfo di;
+    di.clock_khz = clock_khz;
+    return barrier_timeout_ticks(di);
+}
+
 int stream_ctl(hipStream_t stream, Ctl** out, int* cus, long long* clock_khz) {
     std::lock_guard<std::mutex> lk(g_mu);
     Scratch* sc = nullptr;

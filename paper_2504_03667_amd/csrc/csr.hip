@@ -40,6 +40,8 @@
 namespace sssp {
 int set_error(int code, const char* msg);                                     // api.cpp
 int stream_ctl(hipStream_t stream, Ctl** out, int* cus, long long* clock_khz);  // api.cpp
+bool grid_launch_is_plain();                                                    // api.cpp
+long long grid_barrier_ticks(long long clock_khz);                              // api.cpp
 
 namespace {
 
@@ -699,11 +701,18 @@ int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w,
     hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, lab, pkey, hop, lists, cc);
     e = hipGetLastError();
     if (e == hipSuccess) {
-        long long timeout = khz * 10000;  // 10 s per barrier wait
-        void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &lab, &pkey,
-                        &hop, &lists, &cc, &timeout, &ctl};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), dim3(nwg),
-                                       dim3(kCsrThreads), args, 0, s);
+        long long timeout = grid_barrier_ticks(khz);
+        if (grid_launch_is_plain()) {
+            // ordinary launch of the same grid (co-resident by its size), for profilers
+            hipLaunchKernelGGL(k_csr_lc<kCsrThreads>, dim3(nwg), dim3(kCsrThreads), 0, s, row_ptr, col, w, n, src,
+                               dist, pred, lab, pkey, hop, lists, cc, timeout, ctl);
+            e = hipGetLastError();
+        } else {
+            void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &lab, &pkey,
+                            &hop, &lists, &cc, &timeout, &ctl};
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), dim3(nwg),
+                                           dim3(kCsrThreads), args, 0, s);
+        }
     }
     (void)hipFreeAsync(buf, s);
     if (e != hipSuccess) return err(SSSP_EDEVICE, "CSR solve launch: %s", hipGetErrorString(e));

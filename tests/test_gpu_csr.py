@@ -209,3 +209,15 @@ def test_csr_sparse_workload(sp):
         for _ in range(2):
             d2, p2 = sp.csr_solve(rpd, cold, wd, 0)
             assert np.array_equal(d2.cpu().numpy(), ref[0]) and np.array_equal(p2.cpu().numpy(), ref[1])
+
+
+def test_csr_plain_launch(sp, monkeypatch):
+    """The ordinary (non-cooperative) launch that profilers need gives the same results."""
+    rng = np.random.default_rng(923)
+    n = 30000
+    eu, ev, ew = random_edges(rng, n, 3 * n, 1, 500)
+    g = Graph(sp, eu, ev, ew, n, False)
+    monkeypatch.setenv("SSSP_GRID_LAUNCH", "plain")
+    check(sp, g, 0, g.dev_oracle_lists, tag="plain")
+    check(sp, g, 17, g.dev_converted, workgroups=7, tag="plain wg7")
+    monkeypatch.delenv("SSSP_GRID_LAUNCH")
