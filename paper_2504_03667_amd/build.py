@@ -24,22 +24,34 @@ def _run(cmd):
     return r.stderr
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+# Test build: the same sources with pseudo-random pauses before every exchange
+# and barrier arrival (stress_delay), loaded only by the barrier-stress tests.
+SO_STRESS = os.path.join(HERE, "libsssp_stress.so")
+VARIANTS = ((SO, BUILD, []), (SO_STRESS, BUILD + "_stress", ["-DSSSP_STRESS_DELAYS=1"]))
 
-    def compile_one(src):
-        obj = os.path.join(BUILD, src + ".o")
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+
+def build(verbose=False):
+    jobs = []
+    for so, folder, extra in VARIANTS:
+        os.makedirs(folder, exist_ok=True)
+        jobs += [(src, folder, extra) for src in SOURCES]
+
+    def compile_one(job):
+        src, folder, extra = job
+        obj = os.path.join(folder, src + ".o")
+        cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         err = _run(cmd)
         if verbose and err.strip():
             sys.stderr.write(err)
         return obj
 
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = SO + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, SO)
+    with ThreadPoolExecutor(min(len(jobs), os.cpu_count() or 8)) as ex:
+        objs = list(ex.map(compile_one, jobs))
+    for i, (so, _, _) in enumerate(VARIANTS):
+        tmp = so + ".tmp"
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] +
+             objs[i * len(SOURCES):(i + 1) * len(SOURCES)])
+        os.replace(tmp, so)
     return SO
 
 

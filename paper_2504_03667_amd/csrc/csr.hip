@@ -222,6 +222,7 @@ __device__ __forceinline__ bool csr_barrier(CsrCtl* cc, uint32_t b, uint32_t nwg
         if (nwg == 1) {
             if (carry) val = ld_agent(carry);
         } else {
+            stress_delay(b);
             const uint32_t old = __hip_atomic_fetch_add(&cc->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (old == b * nwg - 1) {
                 if (carry) val = ld_agent(carry);

@@ -95,6 +95,23 @@ __device__ __forceinline__ void st_agent(X* p, X v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Barrier stress (the separately built libsssp_stress.so only): before it
+// arrives at an exchange, a workgroup pauses for a pseudo-random 0 to ~25 us
+// chosen by (workgroup, key), so that tests see many arrival orders and late
+// members.  Compiled out of the product library.
+__device__ __forceinline__ void stress_delay(uint32_t key) {
+#ifdef SSSP_STRESS_DELAYS
+    uint32_t h = (blockIdx.x + 1u) * 0x9E3779B9u ^ (key * 0x85EBCA6Bu);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    if ((h & 3u) == 0u)
+        for (uint32_t i = 0, k = (h >> 8) & 7u; i < k; ++i) __builtin_amdgcn_s_sleep(127);
+#else
+    (void)key;
+#endif
+}
+
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return b < a ? b : a; }
 __device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
     return ((uint64_t)d << 32) | v;

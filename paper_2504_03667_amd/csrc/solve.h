@@ -152,6 +152,7 @@ __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, 
     __syncthreads();
     if (members == 1) return true;  // one workgroup: its own barrier orders everything
     if (threadIdx.x == 0) {
+        stress_delay((uint32_t)(stamp ^ (stamp >> 29)));
         __builtin_amdgcn_s_waitcnt(0);
         st_agent(&slot[g].stamp, stamp);
     }
@@ -177,6 +178,7 @@ __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, 
 // words; the last of `members` resets them for the next use.  Returns true in
 // the last member.
 __device__ __forceinline__ bool gang_leave(Bar* bw, uint32_t members) {
+    stress_delay(0xfffffffeu);
     const uint32_t prev = __hip_atomic_fetch_add(&bw->exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (prev != members - 1) return false;
     __hip_atomic_store(&bw->bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -196,6 +198,7 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
         __hip_atomic_fetch_add(&ctl->acc[kStatFallbacks], st.fallbacks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&ctl->acc[kStatBarriers], st.barriers, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    stress_delay(0xffffffffu);
     const uint32_t prev = __hip_atomic_fetch_add(&ctl->b.exit, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == gridDim.x - 1) {
         for (int i = 0; i < kStatCount; ++i) {

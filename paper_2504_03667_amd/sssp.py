@@ -100,55 +100,69 @@ def lib():
         if not os.path.exists(SO):
             from . import build as _b
             _b.build()
-        L = ctypes.CDLL(SO)
-        P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
-        L.sssp_version.restype = ctypes.c_int
-        L.sssp_last_error.restype = ctypes.c_char_p
-        L.sssp_strerror.argtypes = [ctypes.c_int]
-        L.sssp_strerror.restype = ctypes.c_char_p
-        L.sssp_dense_solve.argtypes = [P, I32, I32, P, P, P]
-        L.sssp_dense_solve_ex.argtypes = [P, I64, I32, I32, P, P, U32, ctypes.POINTER(sssp_tuning), P]
-        L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
-        L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
-                                               ctypes.POINTER(sssp_tuning), P]
-        L.sssp_last_trace.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), I32,
-                                      ctypes.POINTER(I32)]
-        L.sssp_last_trace.restype = ctypes.c_int
-        L.sssp_batch_max_n.restype = I32
-        L.sssp_batch_plan_create.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
-                                             ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(P)]
-        L.sssp_batch_plan_launch.argtypes = [P, P]
-        L.sssp_batch_plan_info.argtypes = [P, ctypes.POINTER(sssp_plan_info)]
-        L.sssp_batch_plan_status.argtypes = [P, P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
-        L.sssp_batch_plan_destroy.argtypes = [P]
-        L.sssp_dense_validate.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
-        L.sssp_server_add_graph_ex.argtypes = [P, P, I64, I32, U32, ctypes.POINTER(I32)]
-        L.sssp_server_graph_elem.argtypes = [P, I32, ctypes.POINTER(I32)]
-        L.sssp_edges_to_dense.argtypes = [P, P, P, I64, I32, I32, P, I64, ctypes.POINTER(I64), P]
-        L.sssp_hops.argtypes = [P, P, I32, P, P]
-        L.sssp_paths.argtypes = [P, P, I32, P, I32, P, P, P]
-        L.sssp_single_max_n.restype = I32
-        L.sssp_edges_to_csr.argtypes = [P, P, P, I64, I32, I32, P, P, P, ctypes.POINTER(I64),
-                                        ctypes.POINTER(I64), P]
-        L.sssp_csr_solve.argtypes = [P, P, P, I32, I32, P, P, ctypes.POINTER(sssp_tuning), P]
-        L.sssp_csr_grid.argtypes = [I32, ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(I32), ctypes.POINTER(I32),
-                                    ctypes.POINTER(I32)]
-        L.sssp_server_now_ns.restype = I64
-        L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
-        L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
-        L.sssp_server_submit.argtypes = [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_uint64)]
-        L.sssp_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), I32, ctypes.POINTER(I32)]
-        L.sssp_server_wait.argtypes = [P, ctypes.c_uint64, I64]
-        L.sssp_server_query_info.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(sssp_query_info)]
-        L.sssp_server_get_stats.argtypes = [P, ctypes.POINTER(sssp_server_stats)]
-        L.sssp_server_destroy.argtypes = [P]
-        for name in ("sssp_dense_solve", "sssp_dense_solve_ex", "sssp_last_status",
-                     "sssp_dense_solve_batched", "sssp_server_create", "sssp_server_add_graph",
-                     "sssp_server_submit", "sssp_server_poll", "sssp_server_wait",
-                     "sssp_server_query_info", "sssp_server_get_stats", "sssp_server_destroy"):
-            getattr(L, name).restype = ctypes.c_int
-        _lib = L
+        _lib = _declare(ctypes.CDLL(SO))
     return _lib
+
+
+def use_library(path):
+    """Makes every call of this module go to the library at `path` (a build of the
+    same sources, e.g. the barrier-stress test build); returns the previous one.
+    use_library(None) restores libsssp.so."""
+    global _lib
+    prev = _lib
+    _lib = None if path is None else _declare(ctypes.CDLL(path))
+    return prev
+
+
+def _declare(L):
+    """Argument and result types of the C ABI on a loaded library."""
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.sssp_version.restype = ctypes.c_int
+    L.sssp_last_error.restype = ctypes.c_char_p
+    L.sssp_strerror.argtypes = [ctypes.c_int]
+    L.sssp_strerror.restype = ctypes.c_char_p
+    L.sssp_dense_solve.argtypes = [P, I32, I32, P, P, P]
+    L.sssp_dense_solve_ex.argtypes = [P, I64, I32, I32, P, P, U32, ctypes.POINTER(sssp_tuning), P]
+    L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
+                                           ctypes.POINTER(sssp_tuning), P]
+    L.sssp_last_trace.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), I32,
+                                  ctypes.POINTER(I32)]
+    L.sssp_last_trace.restype = ctypes.c_int
+    L.sssp_batch_max_n.restype = I32
+    L.sssp_batch_plan_create.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
+                                         ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(P)]
+    L.sssp_batch_plan_launch.argtypes = [P, P]
+    L.sssp_batch_plan_info.argtypes = [P, ctypes.POINTER(sssp_plan_info)]
+    L.sssp_batch_plan_status.argtypes = [P, P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    L.sssp_batch_plan_destroy.argtypes = [P]
+    L.sssp_dense_validate.argtypes = [P, I64, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    L.sssp_server_add_graph_ex.argtypes = [P, P, I64, I32, U32, ctypes.POINTER(I32)]
+    L.sssp_server_graph_elem.argtypes = [P, I32, ctypes.POINTER(I32)]
+    L.sssp_edges_to_dense.argtypes = [P, P, P, I64, I32, I32, P, I64, ctypes.POINTER(I64), P]
+    L.sssp_hops.argtypes = [P, P, I32, P, P]
+    L.sssp_paths.argtypes = [P, P, I32, P, I32, P, P, P]
+    L.sssp_single_max_n.restype = I32
+    L.sssp_edges_to_csr.argtypes = [P, P, P, I64, I32, I32, P, P, P, ctypes.POINTER(I64),
+                                    ctypes.POINTER(I64), P]
+    L.sssp_csr_solve.argtypes = [P, P, P, I32, I32, P, P, ctypes.POINTER(sssp_tuning), P]
+    L.sssp_csr_grid.argtypes = [I32, ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                ctypes.POINTER(I32)]
+    L.sssp_server_now_ns.restype = I64
+    L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
+    L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
+    L.sssp_server_submit.argtypes = [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_uint64)]
+    L.sssp_server_poll.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), I32, ctypes.POINTER(I32)]
+    L.sssp_server_wait.argtypes = [P, ctypes.c_uint64, I64]
+    L.sssp_server_query_info.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(sssp_query_info)]
+    L.sssp_server_get_stats.argtypes = [P, ctypes.POINTER(sssp_server_stats)]
+    L.sssp_server_destroy.argtypes = [P]
+    for name in ("sssp_dense_solve", "sssp_dense_solve_ex", "sssp_last_status",
+                 "sssp_dense_solve_batched", "sssp_server_create", "sssp_server_add_graph",
+                 "sssp_server_submit", "sssp_server_poll", "sssp_server_wait",
+                 "sssp_server_query_info", "sssp_server_get_stats", "sssp_server_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
 
 
 def _check(rc):
