@@ -184,6 +184,32 @@ typedef struct sssp_plan_info {
     int32_t lc_candidates;               /* instances whose matrix qualified for it */
 } sssp_plan_info;
 
+/* How a batched launch splits its instances (the item order and gang shapes of
+ * sssp_dense_solve_batched / sssp_batch_plan_create for the given shape
+ * parameters), computed on the host: it touches no device and reads none of the
+ * buffers, only checks the instances' arguments as those calls do.  Entry k of
+ * out (count entries) is the k-th item of the launch: largest n first, then the
+ * instances of a matrix shared by at least 32 of them (each solved by one
+ * workgroup).  An instance with n <= single_max_n (0 = the batch limit) is one
+ * workgroup; a larger one a gang of `parts` workgroups of `columns` columns each
+ * (a multiple of 4; parts = ceil(n / columns), at least 2), sized from
+ * gang_columns (0 = 4096; a multiple of 4) and at most max_parts (0 = 512)
+ * members.  With SSSP_FLAG_LABEL_CORRECTING every unshared instance is a
+ * label-correcting gang (possibly of one) of at most 256 columns per member.
+ * scratch_offset / scratch_bytes: its exchange records and lists in the launch's
+ * arena (-1 / 0 when it has none); *arena_bytes (may be NULL) gets the total.
+ * SSSP_EUNSUPPORTED if an instance would need columns above the batch limit. */
+typedef struct sssp_layout_entry {
+    int32_t instance;        /* index into inst */
+    int32_t parts;           /* workgroups that solve it */
+    int32_t columns;         /* columns per workgroup (n for one workgroup) */
+    int32_t method;          /* 0: Dijkstra rounds, 1: label-correcting */
+    int64_t scratch_offset;  /* byte offset in the arena, -1 if none */
+    int64_t scratch_bytes;
+} sssp_layout_entry;
+int sssp_batch_layout(const sssp_instance* inst, int32_t count, uint32_t flags, int32_t single_max_n,
+                      int32_t gang_columns, int32_t max_parts, sssp_layout_entry* out, int64_t* arena_bytes);
+
 int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,
                            void* stream, sssp_batch_plan** out);
 int sssp_batch_plan_launch(sssp_batch_plan* plan, void* stream);

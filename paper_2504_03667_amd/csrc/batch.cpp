@@ -69,7 +69,8 @@ constexpr int32_t kLcColumns = 256;
 // solved by a gang of workgroups.  lc (may be null): per instance, solve it
 // with the label-correcting method (never for shared matrices).
 int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t single_max_n,
-          int32_t gang_columns, int32_t max_parts, Build* out, const char* lc = nullptr) {
+          int32_t gang_columns, int32_t max_parts, Build* out, const char* lc = nullptr,
+          std::vector<int32_t>* order_out = nullptr) {
     std::vector<int32_t> order(count);
     for (int32_t i = 0; i < count; ++i) order[i] = i;
     std::map<std::pair<const void*, int64_t>, int32_t> uses;
@@ -119,6 +120,7 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
         for (int32_t j = 0; j < b.parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
         out->items.push_back(b);
     }
+    if (order_out) *order_out = order;
     return SSSP_OK;
 }
 
@@ -310,6 +312,35 @@ int lc_candidates(sssp_batch_plan* p, hipStream_t s) {
 extern "C" {
 
 int32_t sssp_batch_max_n(void) { return max_batch_single_n(); }
+
+int sssp_batch_layout(const sssp_instance* inst, int32_t count, uint32_t flags, int32_t single_max_n,
+                      int32_t gang_columns, int32_t max_parts, sssp_layout_entry* out, int64_t* arena_bytes) {
+    int rc = check_all(inst, count);
+    if (rc) return rc;
+    if (!out && count > 0) return err(SSSP_EINVAL, "out is NULL");
+    if (single_max_n < 0 || gang_columns < 0 || max_parts < 0) return err(SSSP_EINVAL, "negative tuning value");
+    if (single_max_n > max_batch_single_n())
+        return err(SSSP_EINVAL, "single_max_n %d above the limit %d", single_max_n, max_batch_single_n());
+    if (gang_columns % 4) return err(SSSP_EINVAL, "gang_columns %d is not a multiple of 4", gang_columns);
+    std::vector<Source> src(count);
+    for (int32_t i = 0; i < count; ++i) src[i] = Source{inst[i].W, inst[i].ld, 4};
+    std::vector<char> lc;
+    if (flags & SSSP_FLAG_LABEL_CORRECTING) lc.assign(count, 1);
+    Build b;
+    std::vector<int32_t> order;
+    rc = build(inst, src.data(), count, single_max_n ? single_max_n : max_batch_single_n(),
+               gang_columns ? gang_columns : 4096, max_parts ? max_parts : 512, &b, lc.empty() ? nullptr : lc.data(),
+               &order);
+    if (rc) return rc;
+    for (int32_t k = 0; k < count; ++k) {
+        const BatchItem& it = b.items[k];
+        const unsigned long long bytes = item_scratch_bytes(it.method, it.parts, it.S, pub_size());
+        out[k] = sssp_layout_entry{order[k], it.parts, it.S, it.method,
+                                   bytes ? (int64_t)it.scratch_off : -1, (int64_t)bytes};
+    }
+    if (arena_bytes) *arena_bytes = (int64_t)b.arena_bytes;
+    return SSSP_OK;
+}
 
 int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w, int32_t* max_finite_w,
                         void* stream) {

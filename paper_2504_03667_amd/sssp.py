@@ -65,6 +65,11 @@ class sssp_instance(ctypes.Structure):
                 ("src", ctypes.c_int32), ("dist", ctypes.c_void_p), ("pred", ctypes.c_void_p)]
 
 
+class sssp_layout_entry(ctypes.Structure):
+    _fields_ = [("instance", ctypes.c_int32), ("parts", ctypes.c_int32), ("columns", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("scratch_offset", ctypes.c_int64), ("scratch_bytes", ctypes.c_int64)]
+
+
 class sssp_server_config(ctypes.Structure):
     _fields_ = [("workgroups", ctypes.c_int32), ("ring_slots", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("single_max_n", ctypes.c_int32),
@@ -130,6 +135,8 @@ def _declare(L):
                                   ctypes.POINTER(I32)]
     L.sssp_last_trace.restype = ctypes.c_int
     L.sssp_batch_max_n.restype = I32
+    L.sssp_batch_layout.argtypes = [ctypes.POINTER(sssp_instance), I32, U32, I32, I32, I32,
+                                    ctypes.POINTER(sssp_layout_entry), ctypes.POINTER(I64)]
     L.sssp_batch_plan_create.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
                                          ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(P)]
     L.sssp_batch_plan_launch.argtypes = [P, P]
@@ -251,6 +258,18 @@ def sssp_dense_solve_batched(items, flags=0, threads=0, workgroups=0, stream=Non
     arr, count = make_instances(items)
     return _check(lib().sssp_dense_solve_batched(arr, count, flags, _tuning(threads, workgroups),
                                                  _stream(stream)))
+
+
+def sssp_batch_layout(instances, flags=0, single_max_n=0, gang_columns=0, max_parts=0):
+    """sssp_batch_layout on an array of sssp_instance (host only: the buffers are
+    not read).  Returns ([entry dicts in launch order], arena bytes)."""
+    count = len(instances)
+    arr = (sssp_instance * max(1, count))(*instances)
+    out = (sssp_layout_entry * max(1, count))()
+    arena = ctypes.c_int64(0)
+    _check(lib().sssp_batch_layout(arr, count, flags, single_max_n, gang_columns, max_parts, out,
+                                   ctypes.byref(arena)))
+    return [{k: getattr(out[i], k) for k, _ in sssp_layout_entry._fields_} for i in range(count)], arena.value
 
 
 def sssp_batch_max_n():
