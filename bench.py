@@ -12,6 +12,7 @@ instances against one-solve-per-launch; plus the HBM roofline of the
 whole-GPU kernel and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import gc
 import json
 import os
 import re
@@ -277,6 +278,10 @@ def bench_served(sp, torch, gen, args):
             srv.poll(1 << 20)
             if replay:
                 # open-loop replay: latency = host-observed completion - scheduled arrival
+                # (Python's garbage collector is paused meanwhile: its pauses would
+                # delay submissions, a property of this harness, not of the server)
+                gc.collect()
+                gc.disable()
                 t0 = sp.sssp_server_now_ns() + 2_000_000
                 tickets = []
                 for q, (d, p) in zip(wl.queries, outs):
@@ -286,6 +291,7 @@ def bench_served(sp, torch, gen, args):
                     tickets.append(srv.submit(gids[q.graph], q.src, d, p))
                 for t in tickets:
                     srv.wait(t, timeout_s=300)
+                gc.enable()
                 lat, svc, t_end, bad = [], [], 0, 0
                 for q, t in zip(wl.queries, tickets):
                     inf = srv.info(t)

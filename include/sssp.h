@@ -328,7 +328,13 @@ typedef struct sssp_server_config {
                                (exchanges per round vs rows streamed) finds it cheaper (0 = 64; < 0 = never) */
     int32_t lc_gang_columns;  /* columns per gang member of label-correcting queries (0 = 1024) */
     int32_t lc_model;       /* < 0: switch on lc_rounds alone, without the cost model (0 = use it) */
-    int32_t reserved[4];
+    int32_t idle_gang_columns;  /* latency mode: a gang query admitted while no other query waits is
+                                   split into slices of this many columns (or wider, to fit in three
+                                   quarters of the workgroups minus those in flight), for lower
+                                   latency when the server is not saturated; Dijkstra and
+                                   label-correcting gangs alike (0 = max(256, gang_columns / 4);
+                                   < 0 = off: always gang_columns / lc_gang_columns) */
+    int32_t reserved[3];
 } sssp_server_config;
 
 /* query states */

@@ -79,6 +79,7 @@ struct Query {
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     int32_t status = 0, rounds = 0;
     int64_t settled = 0;
+    bool replanned = false;  // admission has considered the latency-mode split
 };
 
 // First-fit allocator over the scratch arena.
@@ -175,14 +176,14 @@ struct sssp_server {
     // columns per gang member and number of members for an n-vertex query;
     // label-correcting queries are spread over narrow slices (their sweeps read
     // several times the rows of a Dijkstra solve)
-    void plan(int32_t n, int32_t method, int32_t* parts, int32_t* S) const {
+    void plan(int32_t n, int32_t method, int32_t* parts, int32_t* S, int32_t columns = 0) const {
         const bool lc = method == kMethodLabelCorrecting;
         if (!lc && n <= cfg.single_max_n) {
             *parts = 1;
             *S = n;
             return;
         }
-        const int32_t cols = lc ? cfg.lc_gang_columns : cfg.gang_columns;
+        const int32_t cols = columns > 0 ? columns : lc ? cfg.lc_gang_columns : cfg.gang_columns;
         int64_t p = ((int64_t)n + cols - 1) / cols;
         const int64_t pmin = ((int64_t)n + max_serve_slice() - 1) / max_serve_slice();
         p = std::max<int64_t>(p, std::max<int64_t>(lc ? 1 : 2, pmin));
@@ -219,6 +220,28 @@ struct sssp_server {
         while (!pending.empty()) {
             Query& q = queries[pending.front() - 1];
             if (free_slots.empty()) break;
+            // latency mode: a gang query that nothing waits behind is split into
+            // narrower slices (more members, shorter rounds), as narrow as
+            // idle_gang_columns allows within three quarters of the workgroups minus
+            // those in flight; under load the wide default keeps the workgroup time
+            // per query, and so the throughput, lower
+            if (!q.replanned && q.parts > 1 && cfg.idle_gang_columns > 0 && pending.size() == 1) {
+                q.replanned = true;
+                const int32_t n = graphs[q.graph].n;
+                const int64_t budget = (int64_t)nwg * 3 / 4 - ring_used;
+                const int32_t wide = q.method == kMethodLabelCorrecting ? cfg.lc_gang_columns : cfg.gang_columns;
+                int32_t cols = std::min(cfg.idle_gang_columns, wide);
+                if (budget > q.parts && ((int64_t)n + cols - 1) / cols > budget)
+                    cols = (int32_t)((((int64_t)n + budget - 1) / budget + 3) & ~int64_t(3));
+                int32_t p2 = 0, S2 = 0;
+                plan(n, q.method, &p2, &S2, cols);
+                const uint64_t b2 = footprint(q.method, p2, S2);
+                if (budget > q.parts && p2 > q.parts && p2 <= budget && b2 <= (uint64_t)cfg.scratch_bytes) {
+                    q.parts = p2;
+                    q.S = S2;
+                    q.bytes = b2;
+                }
+            }
             if (ring_used + q.parts > cfg.ring_slots) break;
             uint64_t off = 0;
             if (q.bytes && !arena_alloc.alloc(q.bytes, &off)) break;
@@ -406,6 +429,8 @@ int sssp_server_create(const sssp_server_config* cfg_in, sssp_server** out) {
     if (c.lc_rounds == 0) c.lc_rounds = 64;
     if (c.lc_gang_columns <= 0) c.lc_gang_columns = 1024;
     c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
+    if (c.idle_gang_columns == 0) c.idle_gang_columns = std::max(256, c.gang_columns / 4);
+    if (c.idle_gang_columns > 0) c.idle_gang_columns = (c.idle_gang_columns + 3) & ~3;
     if (c.single_max_n > max_serve_single_n() || c.gang_columns > max_serve_slice() || c.gang_columns % 4)
         return release_all(s), err(SSSP_EINVAL, "single_max_n <= %d and gang_columns <= %d (multiple of 4) required",
                                    max_serve_single_n(), max_serve_slice());

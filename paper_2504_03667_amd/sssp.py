@@ -77,7 +77,7 @@ class sssp_server_config(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int64),
                 ("idle_park_ms", ctypes.c_int32), ("lc_rounds", ctypes.c_int32),
                 ("lc_gang_columns", ctypes.c_int32), ("lc_model", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("idle_gang_columns", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class sssp_query_info(ctypes.Structure):

@@ -210,3 +210,41 @@ def test_server_label_correcting(sp):
                 assert info["status"] & 3 == 0 and info["method"] == 1, (forced, info)
                 dr, pr, _ = oracle.dijkstra(graphs[g], src)
                 assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), (forced, g, src)
+
+
+def test_server_latency_mode_gangs(sp):
+    """A gang query admitted while nothing waits behind it is split into narrower
+    slices (idle_gang_columns); a burst keeps the wide default.  Results are the
+    oracle's either way."""
+    rng = np.random.default_rng(205)
+    graphs = make_graphs(rng, [3000, 5000])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    with sp.Server(single_max_n=1024, gang_columns=2048, idle_gang_columns=256) as srv:
+        gids = [srv.add_graph(W) for W in dev]
+        # one at a time: narrow slices
+        for g in (0, 1):
+            n = graphs[g].shape[0]
+            d, p = outputs(n)
+            t = srv.submit(gids[g], 1, d, p)
+            srv.wait(t, timeout_s=60)
+            info = srv.info(t)
+            dr, pr, _ = oracle.dijkstra(graphs[g], 1)
+            assert info["parts"] == -(-n // 256), info
+            assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr)
+        # a burst: queries behind the first keep the wide split
+        outs = [outputs(graphs[k % 2].shape[0]) for k in range(40)]
+        ts = [srv.submit(gids[k % 2], 7 + k, *outs[k]) for k in range(40)]
+        parts = []
+        for k, t in enumerate(ts):
+            srv.wait(t, timeout_s=60)
+            info = srv.info(t)
+            parts.append(info["parts"])
+            dr, pr, _ = oracle.dijkstra(graphs[k % 2], 7 + k)
+            assert np.array_equal(outs[k][0].cpu().numpy(), dr) and np.array_equal(outs[k][1].cpu().numpy(), pr)
+        assert parts.count(2) + parts.count(3) >= 10, parts  # wide: ceil(n / 2048) members
+    with sp.Server(single_max_n=1024, gang_columns=2048, idle_gang_columns=-1) as srv:
+        gid = srv.add_graph(dev[1])
+        d, p = outputs(5000)
+        t = srv.submit(gid, 3, d, p)
+        srv.wait(t, timeout_s=60)
+        assert srv.info(t)["parts"] == 3
