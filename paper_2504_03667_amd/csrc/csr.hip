@@ -98,37 +98,65 @@ __global__ void k_csr_degree(const int32_t* __restrict__ eu, const int32_t* __re
     }
 }
 
-// row_ptr[0] = 0, row_ptr[i + 1] = row_ptr[i] + deg[i]: one workgroup, chunk by chunk.
-__global__ __launch_bounds__(1024) void k_csr_scan(const uint32_t* __restrict__ deg, int32_t n,
-                                                   int64_t* __restrict__ row_ptr) {
-    __shared__ unsigned long long wsum[16];
-    __shared__ unsigned long long carry;
-    if (threadIdx.x == 0) {
-        carry = 0;
-        row_ptr[0] = 0;
+// row_ptr[0] = 0, row_ptr[i + 1] = row_ptr[i] + deg[i], in three passes over
+// chunks of 1024 vertices: each chunk's total, an exclusive scan of the totals
+// (one workgroup), then each chunk's scan plus its offset.
+constexpr int kScanChunk = 1024;
+
+// Inclusive scan of one value per thread over a workgroup of kScanChunk
+// threads; *total gets the workgroup's sum.
+__device__ __forceinline__ unsigned long long wg_inclusive_scan(unsigned long long x, unsigned long long* wsum,
+                                                                unsigned long long* total) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, (unsigned)o, 64);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
     __syncthreads();
-    for (int32_t base = 0; base < n; base += 1024) {
-        const int32_t i = base + (int32_t)threadIdx.x;
-        unsigned long long x = i < n ? deg[i] : 0ull;
-        // inclusive scan within the wave
-        const int lane = threadIdx.x & 63;
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long y = __shfl_up(x, (unsigned)o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[threadIdx.x >> 6] = x;
-        __syncthreads();
-        unsigned long long before = 0, total = 0;
-        for (int k = 0; k < 16; ++k) {
-            if (k < (int)(threadIdx.x >> 6)) before += wsum[k];
-            total += wsum[k];
-        }
-        if (i < n) row_ptr[i + 1] = (int64_t)(carry + before + x);
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
+    unsigned long long before = 0, sum = 0;
+    for (int k = 0; k < kScanChunk / 64; ++k) {
+        if (k < (int)(threadIdx.x >> 6)) before += wsum[k];
+        sum += wsum[k];
     }
+    __syncthreads();  // wsum is reused by the next call
+    *total = sum;
+    return before + x;
+}
+
+__global__ __launch_bounds__(kScanChunk) void k_csr_chunk_sums(const uint32_t* __restrict__ deg, int32_t n,
+                                                               unsigned long long* __restrict__ sums) {
+    __shared__ unsigned long long wsum[kScanChunk / 64];
+    const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    unsigned long long total = 0;
+    (void)wg_inclusive_scan(i < n ? deg[i] : 0ull, wsum, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk totals in place; row_ptr[0] = 0.
+__global__ __launch_bounds__(kScanChunk) void k_csr_scan_sums(unsigned long long* __restrict__ sums, int32_t chunks,
+                                                              int64_t* __restrict__ row_ptr) {
+    __shared__ unsigned long long wsum[kScanChunk / 64];
+    unsigned long long carry = 0;
+    if (threadIdx.x == 0) row_ptr[0] = 0;
+    for (int32_t base = 0; base < chunks; base += kScanChunk) {
+        const int32_t i = base + (int32_t)threadIdx.x;
+        const unsigned long long x = i < chunks ? sums[i] : 0ull;
+        unsigned long long total = 0;
+        const unsigned long long incl = wg_inclusive_scan(x, wsum, &total);
+        if (i < chunks) sums[i] = carry + incl - x;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanChunk) void k_csr_scan_chunks(const uint32_t* __restrict__ deg, int32_t n,
+                                                                const unsigned long long* __restrict__ sums,
+                                                                int64_t* __restrict__ row_ptr) {
+    __shared__ unsigned long long wsum[kScanChunk / 64];
+    const int64_t i = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
+    unsigned long long total = 0;
+    const unsigned long long incl = wg_inclusive_scan(i < n ? deg[i] : 0ull, wsum, &total);
+    if (i < n) row_ptr[i + 1] = (int64_t)(sums[blockIdx.x] + incl);
 }
 
 __global__ void k_csr_fill(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
@@ -636,14 +664,17 @@ int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, i
     if (!row_ptr || n < 1 || m < 0 || (m > 0 && (!eu || !ev || !ew || !col || !w)))
         return err(SSSP_EINVAL, "bad arguments (n=%d m=%lld)", n, (long long)m);
     hipStream_t s = (hipStream_t)stream;
-    // scratch: degrees, then cursors (n words each), and the bad-edge counter
+    // scratch: degrees, then cursors (n words each), the bad-edge counter and the
+    // per-chunk totals of the scan
+    const int32_t chunks = (int32_t)(((int64_t)n + kScanChunk - 1) / kScanChunk);
     char* buf = nullptr;
-    const size_t bytes = 2 * sizeof(uint32_t) * (size_t)n + sizeof(unsigned long long);
+    const size_t bytes = 2 * sizeof(uint32_t) * (size_t)n + sizeof(unsigned long long) * (1 + (size_t)chunks);
     hipError_t e = hipMallocAsync((void**)&buf, bytes, s);
     if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync: %s", hipGetErrorString(e));
     uint32_t* deg = reinterpret_cast<uint32_t*>(buf);
     uint32_t* cursor = deg + n;
     unsigned long long* bad = reinterpret_cast<unsigned long long*>(cursor + n);
+    unsigned long long* sums = bad + 1;
     e = zero_fill(buf, (bytes + 3) & ~size_t(3), s);
     const unsigned eb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (m + 255) / 256), 8192);
     const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
@@ -652,7 +683,9 @@ int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, i
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(1024), 0, s, deg, n, row_ptr);
+        hipLaunchKernelGGL(k_csr_chunk_sums, dim3(chunks), dim3(kScanChunk), 0, s, deg, n, sums);
+        hipLaunchKernelGGL(k_csr_scan_sums, dim3(1), dim3(kScanChunk), 0, s, sums, chunks, row_ptr);
+        hipLaunchKernelGGL(k_csr_scan_chunks, dim3(chunks), dim3(kScanChunk), 0, s, deg, n, sums, row_ptr);
         e = hipGetLastError();
     }
     if (e == hipSuccess && m > 0) {
