@@ -75,6 +75,12 @@ def test_plans_all_configurations(sp):
                 assert info["graph"] == 1
                 if cfg:
                     assert info["single_max_n"] == cfg["single_max_n"]
+                    # the host-side layout query describes the launch the plan runs
+                    from paper_2504_03667_amd import sssp
+                    arr, count = sssp.make_instances(items)
+                    entries, _ = sp.sssp_batch_layout(list(arr[:count]), 0, cfg["single_max_n"],
+                                                      cfg.get("gang_columns", 0), max(2, info["workgroups"] // 2))
+                    assert max(e["parts"] for e in entries) == info["max_parts"]
                 else:
                     assert info["candidates"] >= 2
                 if cfg.get("single_max_n", 16384) < 4100:
@@ -214,3 +220,23 @@ def test_plan_chooses_label_correcting_for_many_levels(sp):
             assert info["lc_candidates"] == sparse
             assert info["lc_instances"] in (0, sparse)
             check_items(graphs, items, refs, {})
+
+
+def test_compact_plan_large_offsets(sp):
+    """A uint8 compact copy whose row offsets pass 2^31 bytes (n = 50000), solved by
+    gangs of one column group per thread, against the oracle."""
+    spec = gen.GraphSpec(50000, 0.002, 1, 200, 77001)
+    W = gen.dense_device(spec)
+    items = [(W, src, torch.full((spec.n,), -9, dtype=torch.int32, device="cuda"),
+              torch.full((spec.n,), -9, dtype=torch.int32, device="cuda")) for src in (0, 49999)]
+    with sp.BatchPlan(items, sp.SSSP_FLAG_COMPACT, single_max_n=4096, gang_columns=2048) as plan:
+        plan.launch()
+        status, _ = plan.status()
+        assert status & 3 == 0
+        assert plan.info()["compact_graphs"] == 1
+    del W
+    torch.cuda.empty_cache()
+    Wh = gen.dense_host(spec)
+    for _, src, d, p in items:
+        dr, pr, _ = oracle.dijkstra(Wh, src)
+        assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), src
