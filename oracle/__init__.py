@@ -41,6 +41,8 @@ def lib():
         L.oracle_dijkstra_iters.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P, P,
                                             P, ctypes.c_int32, ctypes.c_int32]
         L.oracle_dijkstra_iters.restype = ctypes.c_int64
+        L.oracle_dijkstra_every_source.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, P]
+        L.oracle_dijkstra_every_source.restype = ctypes.c_int
         L.oracle_floyd_warshall.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P]
         L.oracle_floyd_warshall.restype = ctypes.c_int
         L.oracle_bellman_ford.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
@@ -79,6 +81,18 @@ def _mat(W):
 
 def _threads(t):
     return t or max(1, min(16, os.cpu_count() or 1))
+
+
+def dijkstra_every_source(Ws):
+    """Algorithm 1 from every source of each matrix in Ws ([count, n, n] int32):
+    returns (dist, pred), each [count, n (source), n]."""
+    Ws = np.ascontiguousarray(Ws, np.int32)
+    count, n, _ = Ws.shape
+    dist = np.empty((count, n, n), np.int32)
+    pred = np.empty((count, n, n), np.int32)
+    if lib().oracle_dijkstra_every_source(Ws.ctypes.data, count, n, dist.ctypes.data, pred.ctypes.data) != 0:
+        raise ValueError("bad arguments")
+    return dist, pred
 
 
 def dijkstra(W, src, early_exit=True, with_order=False):

@@ -12,6 +12,8 @@
  *
  * Functions
  *   oracle_dijkstra        Algorithm 1 of the paper, step by step (serial).
+ *   oracle_dijkstra_every_source  the same from every source of many tiny
+ *                          matrices (a loop, for exhaustive pins).
  *   oracle_floyd_warshall  textbook all-pairs distances (dist only).
  *   oracle_bellman_ford    textbook single-source distances (dist only).
  *   oracle_certificate     shortest-path certificate of (dist, pred), O(n^2).
@@ -95,6 +97,22 @@ int64_t oracle_dijkstra(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
                         int32_t* pred, int32_t* order, int32_t early_exit)
 {
     return oracle_dijkstra_iters(W, ld, n, src, dist, pred, order, early_exit, 0);
+}
+
+/* Algorithm 1 from every source of each of `count` n x n matrices stored one
+ * after another (row stride n): dist and pred get count x n x n entries, [g][s][v].
+ * A loop over oracle_dijkstra for exhaustive pins over many tiny graphs.
+ * Returns 0, or -1 on bad arguments. */
+int oracle_dijkstra_every_source(const int32_t* Ws, int64_t count, int32_t n, int32_t* dist, int32_t* pred)
+{
+    if (!Ws || !dist || !pred || count < 0 || n < 1) return -1;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t g = 0; g < count; ++g)
+        for (int32_t s = 0; s < n; ++s)
+            if (oracle_dijkstra(Ws + g * nn, n, n, s, dist + g * nn + (int64_t)s * n, pred + g * nn + (int64_t)s * n,
+                                0, 1) < 0)
+                return -1;
+    return 0;
 }
 
 /* Textbook Floyd-Warshall over the matrix; D is n x n int64, OR_INF64 = no path.

@@ -229,3 +229,37 @@ def test_saturating_path_lengths_stay_unreachable():
     W = from_edges(3, [(0, 1, big), (1, 2, 5)], directed=True)
     d, p, _ = oracle.dijkstra(W, 0)
     assert d.tolist() == [0, big, INF] and p.tolist() == [-1, 0, -1]
+
+
+def test_exhaustive_directed_n4():
+    """All 3^12 directed 4-vertex graphs with arc weights in {1, 2, inf}, every source:
+    dist against Floyd-Warshall computed here (vectorised over all graphs), and pred
+    against the (dist[u], u)-lexmin tight tail, which is Algorithm 1's pred when every
+    weight is at least 1 (settle order = (dist, index))."""
+    n = 4
+    arcs = [(i, j) for i in range(n) for j in range(n) if i != j]
+    vals = np.array([1, 2, INF], np.int64)
+    digits = (np.arange(3 ** len(arcs))[:, None] // 3 ** np.arange(len(arcs))[None, :]) % 3
+    G = np.full((3 ** len(arcs), n, n), INF, np.int64)
+    G[:, np.arange(n), np.arange(n)] = 0
+    for k, (i, j) in enumerate(arcs):
+        G[:, i, j] = vals[digits[:, k]]
+    dist, pred = oracle.dijkstra_every_source(G.astype(np.int32))
+    # Floyd-Warshall, all graphs at once (int64, INF as a large sentinel)
+    BIG = np.int64(1) << 40
+    D = np.where(G == INF, BIG, G)
+    for k in range(n):
+        D = np.minimum(D, D[:, :, k, None] + D[:, None, k, :])
+    want = np.where(D >= BIG, INF, D)
+    assert np.array_equal(dist.astype(np.int64), want)
+    # pred: over tails u != v with a tight finite arc, the smallest (dist[u], u)
+    du = dist.astype(np.int64)[:, :, :, None]            # [g, s, u, 1]
+    dv = dist.astype(np.int64)[:, :, None, :]            # [g, s, 1, v]
+    w = G[:, None, :, :]                                   # [g, 1, u, v]
+    u_idx = np.arange(n)[None, None, :, None]
+    tight = (w != INF) & (du != INF) & (dv != INF) & (du + w == dv) & (u_idx != np.arange(n)[None, None, None, :])
+    key = np.where(tight, du * n + u_idx, np.iinfo(np.int64).max)
+    best = key.min(axis=2)                                 # [g, s, v]
+    lex = np.where(best == np.iinfo(np.int64).max, -1, best % n)
+    lex[:, np.arange(n), np.arange(n)] = -1                # the source has no pred
+    assert np.array_equal(pred.astype(np.int64), lex)
