@@ -182,7 +182,7 @@ def test_determinism(sp):
     spec = gen.GraphSpec(5000, 0.02, 1, 10, 55)
     Wt = gen.dense_device(spec)
     ref = None
-    for rep in range(20):
+    for rep in range(100):
         d, p, status, _ = run(sp, Wt, 17, 0)
         if ref is None:
             ref = (d, p)
