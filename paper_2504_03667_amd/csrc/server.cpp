@@ -119,6 +119,82 @@ struct Arena {
 
 }  // namespace
 
+// Host policy of the server, free of any device state (so that it can be
+// queried and tested without a GPU): configuration defaults, the gang shape of
+// a query, and the latency-mode split at admission.
+namespace {
+
+int normalize(sssp_server_config& c) {
+    if (c.ring_slots <= 0) c.ring_slots = 4096;
+    if (c.max_inflight <= 0) c.max_inflight = 1024;
+    if (c.single_max_n <= 0) c.single_max_n = 4096;
+    if (c.gang_columns <= 0) c.gang_columns = 2048;
+    if (c.scratch_bytes <= 0) c.scratch_bytes = 256ll << 20;
+    if (c.watchdog_ms <= 0) c.watchdog_ms = 2000;
+    if (c.idle_park_ms <= 0) c.idle_park_ms = 20;
+    if (c.lc_rounds == 0) c.lc_rounds = 64;
+    if (c.lc_gang_columns <= 0) c.lc_gang_columns = 1024;
+    c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
+    if (c.idle_gang_columns == 0) c.idle_gang_columns = std::max(256, c.gang_columns / 4);
+    if (c.idle_gang_columns > 0) c.idle_gang_columns = (c.idle_gang_columns + 3) & ~3;
+    if (c.single_max_n > max_serve_single_n() || c.gang_columns > max_serve_slice() || c.gang_columns % 4)
+        return err(SSSP_EINVAL, "single_max_n <= %d and gang_columns <= %d (multiple of 4) required",
+                   max_serve_single_n(), max_serve_slice());
+    return SSSP_OK;
+}
+
+// Columns per gang member and number of members for an n-vertex query on a
+// kernel of nwg workgroups; label-correcting queries are spread over narrow
+// slices (their sweeps read several times the rows of a Dijkstra solve).
+// `columns` > 0 overrides the configured width.
+void gang_shape(const sssp_server_config& cfg, int nwg, int32_t n, int32_t method, int32_t* parts, int32_t* S,
+                int32_t columns = 0) {
+    const bool lc = method == kMethodLabelCorrecting;
+    if (!lc && n <= cfg.single_max_n) {
+        *parts = 1;
+        *S = n;
+        return;
+    }
+    const int32_t cols = columns > 0 ? columns : lc ? cfg.lc_gang_columns : cfg.gang_columns;
+    int64_t p = ((int64_t)n + cols - 1) / cols;
+    const int64_t pmin = ((int64_t)n + max_serve_slice() - 1) / max_serve_slice();
+    p = std::max<int64_t>(p, std::max<int64_t>(lc ? 1 : 2, pmin));
+    p = std::min<int64_t>(p, std::max(2, nwg / 2));
+    int64_t s = ((int64_t)n + p - 1) / p;
+    s = (s + 3) & ~int64_t(3);
+    *parts = (int32_t)(((int64_t)n + s - 1) / s);
+    *S = (int32_t)s;
+}
+
+uint64_t footprint(int32_t method, int32_t parts, int32_t S) {
+    return item_scratch_bytes(method, parts, S, pub_size());
+}
+
+// Latency mode: a gang query that nothing waits behind is split into narrower
+// slices (more members, shorter rounds), as narrow as idle_gang_columns allows
+// within three quarters of the workgroups minus `busy` (those of the queries in
+// flight); under load the wide split keeps the workgroup time per query, and so
+// the throughput, lower.  Updates parts / S / bytes when it narrows the split.
+void latency_split(const sssp_server_config& cfg, int nwg, int64_t busy, int32_t n, int32_t method, int32_t* parts,
+                   int32_t* S, uint64_t* bytes) {
+    if (*parts <= 1 || cfg.idle_gang_columns <= 0) return;
+    const int64_t budget = (int64_t)nwg * 3 / 4 - busy;
+    const int32_t wide = method == kMethodLabelCorrecting ? cfg.lc_gang_columns : cfg.gang_columns;
+    int32_t cols = std::min(cfg.idle_gang_columns, wide);
+    if (budget > *parts && ((int64_t)n + cols - 1) / cols > budget)
+        cols = (int32_t)((((int64_t)n + budget - 1) / budget + 3) & ~int64_t(3));
+    int32_t p2 = 0, S2 = 0;
+    gang_shape(cfg, nwg, n, method, &p2, &S2, cols);
+    const uint64_t b2 = footprint(method, p2, S2);
+    if (budget > *parts && p2 > *parts && p2 <= budget && b2 <= (uint64_t)cfg.scratch_bytes) {
+        *parts = p2;
+        *S = S2;
+        *bytes = b2;
+    }
+}
+
+}  // namespace
+
 struct sssp_server {
     int device = 0;
     sssp_server_config cfg{};
@@ -173,25 +249,8 @@ struct sssp_server {
         return a;
     }
 
-    // columns per gang member and number of members for an n-vertex query;
-    // label-correcting queries are spread over narrow slices (their sweeps read
-    // several times the rows of a Dijkstra solve)
-    void plan(int32_t n, int32_t method, int32_t* parts, int32_t* S, int32_t columns = 0) const {
-        const bool lc = method == kMethodLabelCorrecting;
-        if (!lc && n <= cfg.single_max_n) {
-            *parts = 1;
-            *S = n;
-            return;
-        }
-        const int32_t cols = columns > 0 ? columns : lc ? cfg.lc_gang_columns : cfg.gang_columns;
-        int64_t p = ((int64_t)n + cols - 1) / cols;
-        const int64_t pmin = ((int64_t)n + max_serve_slice() - 1) / max_serve_slice();
-        p = std::max<int64_t>(p, std::max<int64_t>(lc ? 1 : 2, pmin));
-        p = std::min<int64_t>(p, std::max(2, nwg / 2));
-        int64_t s = ((int64_t)n + p - 1) / p;
-        s = (s + 3) & ~int64_t(3);
-        *parts = (int32_t)(((int64_t)n + s - 1) / s);
-        *S = (int32_t)s;
+    void plan(int32_t n, int32_t method, int32_t* parts, int32_t* S) const {
+        gang_shape(cfg, nwg, n, method, parts, S);
     }
 
     // Workgroup time of a query of g, from a completed Dijkstra query q: the
@@ -210,9 +269,6 @@ struct sssp_server {
         return t_lc < 0.8 * t_dij;
     }
 
-    static uint64_t footprint(int32_t method, int32_t parts, int32_t S) {
-        return item_scratch_bytes(method, parts, S, pub_size());
-    }
 
     // publish as many pending queries as fit; caller holds mu
     void admit() {
@@ -220,27 +276,9 @@ struct sssp_server {
         while (!pending.empty()) {
             Query& q = queries[pending.front() - 1];
             if (free_slots.empty()) break;
-            // latency mode: a gang query that nothing waits behind is split into
-            // narrower slices (more members, shorter rounds), as narrow as
-            // idle_gang_columns allows within three quarters of the workgroups minus
-            // those in flight; under load the wide default keeps the workgroup time
-            // per query, and so the throughput, lower
-            if (!q.replanned && q.parts > 1 && cfg.idle_gang_columns > 0 && pending.size() == 1) {
+            if (!q.replanned && pending.size() == 1) {
                 q.replanned = true;
-                const int32_t n = graphs[q.graph].n;
-                const int64_t budget = (int64_t)nwg * 3 / 4 - ring_used;
-                const int32_t wide = q.method == kMethodLabelCorrecting ? cfg.lc_gang_columns : cfg.gang_columns;
-                int32_t cols = std::min(cfg.idle_gang_columns, wide);
-                if (budget > q.parts && ((int64_t)n + cols - 1) / cols > budget)
-                    cols = (int32_t)((((int64_t)n + budget - 1) / budget + 3) & ~int64_t(3));
-                int32_t p2 = 0, S2 = 0;
-                plan(n, q.method, &p2, &S2, cols);
-                const uint64_t b2 = footprint(q.method, p2, S2);
-                if (budget > q.parts && p2 > q.parts && p2 <= budget && b2 <= (uint64_t)cfg.scratch_bytes) {
-                    q.parts = p2;
-                    q.S = S2;
-                    q.bytes = b2;
-                }
+                latency_split(cfg, nwg, ring_used, graphs[q.graph].n, q.method, &q.parts, &q.S, &q.bytes);
             }
             if (ring_used + q.parts > cfg.ring_slots) break;
             uint64_t off = 0;
@@ -413,27 +451,35 @@ extern "C" {
 
 int64_t sssp_server_now_ns(void) { return now_ns(); }
 
+int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t busy,
+                      int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes) {
+    if (!parts || !columns || workgroups < 1 || n < 1 || (method != kMethodDijkstra && method != kMethodLabelCorrecting) ||
+        busy < 0 || waiting < 0)
+        return err(SSSP_EINVAL, "bad arguments (workgroups=%d n=%d method=%d busy=%d waiting=%d)", workgroups, n,
+                   method, busy, waiting);
+    sssp_server_config c{};
+    if (cfg) c = *cfg;
+    if (int rc = normalize(c)) return rc;
+    int32_t p = 0, S = 0;
+    gang_shape(c, workgroups, n, method, &p, &S);
+    uint64_t bytes = footprint(method, p, S);
+    if (bytes > (uint64_t)c.scratch_bytes)
+        return err(SSSP_ENOMEM, "query needs %llu scratch bytes, arena has %lld", (unsigned long long)bytes,
+                   (long long)c.scratch_bytes);
+    if (waiting == 0) latency_split(c, workgroups, busy, n, method, &p, &S, &bytes);
+    *parts = p;
+    *columns = S;
+    if (scratch_bytes) *scratch_bytes = (int64_t)bytes;
+    return SSSP_OK;
+}
+
 int sssp_server_create(const sssp_server_config* cfg_in, sssp_server** out) {
     if (!out) return err(SSSP_EINVAL, "out is NULL");
     *out = nullptr;
     sssp_server* s = new sssp_server();
     if (cfg_in) s->cfg = *cfg_in;
     sssp_server_config& c = s->cfg;
-    if (c.ring_slots <= 0) c.ring_slots = 4096;
-    if (c.max_inflight <= 0) c.max_inflight = 1024;
-    if (c.single_max_n <= 0) c.single_max_n = 4096;
-    if (c.gang_columns <= 0) c.gang_columns = 2048;
-    if (c.scratch_bytes <= 0) c.scratch_bytes = 256ll << 20;
-    if (c.watchdog_ms <= 0) c.watchdog_ms = 2000;
-    if (c.idle_park_ms <= 0) c.idle_park_ms = 20;
-    if (c.lc_rounds == 0) c.lc_rounds = 64;
-    if (c.lc_gang_columns <= 0) c.lc_gang_columns = 1024;
-    c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
-    if (c.idle_gang_columns == 0) c.idle_gang_columns = std::max(256, c.gang_columns / 4);
-    if (c.idle_gang_columns > 0) c.idle_gang_columns = (c.idle_gang_columns + 3) & ~3;
-    if (c.single_max_n > max_serve_single_n() || c.gang_columns > max_serve_slice() || c.gang_columns % 4)
-        return release_all(s), err(SSSP_EINVAL, "single_max_n <= %d and gang_columns <= %d (multiple of 4) required",
-                                   max_serve_single_n(), max_serve_slice());
+    if (int rc = normalize(c)) return release_all(s), rc;
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) return release_all(s), err(SSSP_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     int cus = 0, rate = 0, per_cu = 0;
@@ -528,7 +574,7 @@ int sssp_server_submit(sssp_server* s, int32_t graph_id, int32_t src, int32_t* d
                     (s->cfg.lc_rounds > 0 && g.max_rounds >= s->cfg.lc_rounds && (s->cfg.lc_model < 0 || g.lc_cheaper == 1));
     q.method = lc ? kMethodLabelCorrecting : kMethodDijkstra;
     s->plan(g.n, q.method, &q.parts, &q.S);
-    q.bytes = sssp_server::footprint(q.method, q.parts, q.S);
+    q.bytes = footprint(q.method, q.parts, q.S);
     if (q.bytes > (uint64_t)s->cfg.scratch_bytes)
         return err(SSSP_ENOMEM, "query needs %llu scratch bytes, arena has %lld", (unsigned long long)q.bytes,
                    (long long)s->cfg.scratch_bytes);

@@ -156,6 +156,8 @@ def _declare(L):
     L.sssp_csr_grid.argtypes = [I32, ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                 ctypes.POINTER(I32)]
     L.sssp_server_now_ns.restype = I64
+    L.sssp_server_shape.argtypes = [ctypes.POINTER(sssp_server_config), I32, I32, I32, I32, I32,
+                                    ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64)]
     L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
     L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
     L.sssp_server_submit.argtypes = [P, I32, I32, P, P, ctypes.POINTER(ctypes.c_uint64)]
@@ -466,6 +468,17 @@ def csr_solve(row_ptr, col, w, src, workgroups=0, stream=None):
 
 def sssp_server_now_ns():
     return lib().sssp_server_now_ns()
+
+
+def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, **cfg):
+    """sssp_server_shape (host only): (parts, columns, scratch_bytes) of an n-vertex query."""
+    c = sssp_server_config()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    parts, cols, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().sssp_server_shape(ctypes.byref(c), workgroups, n, method, busy, waiting, ctypes.byref(parts),
+                                   ctypes.byref(cols), ctypes.byref(b)))
+    return parts.value, cols.value, b.value
 
 
 def sssp_server_create(**cfg):

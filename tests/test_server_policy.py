@@ -1,0 +1,96 @@
+"""Host policy of the server, on the CPU (sssp_server_shape: the split admission
+gives a query, without a device): one workgroup up to single_max_n; gangs of
+gang_columns (label-correcting: lc_gang_columns) per member, at least two
+members, at most half the kernel's workgroups; the latency-mode split (narrower
+slices when nothing waits, within three quarters of the workgroups minus those
+busy); arena bytes; argument errors."""
+import pytest
+
+DIJ, LC = 0, 1
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import paper_2504_03667_amd as m
+    from paper_2504_03667_amd import sssp
+    return m, sssp
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+def check_split(n, parts, cols):
+    assert cols % 4 == 0 and parts * cols >= n and (parts - 1) * cols < n
+
+
+def test_single_and_wide_gangs(sp):
+    m, _ = sp
+    # one workgroup up to single_max_n, also with a backlog
+    assert m.sssp_server_shape(248, 4096, waiting=5)[:2] == (1, 4096)
+    assert m.sssp_server_shape(248, 1, waiting=0)[:2] == (1, 1)
+    for n in (4097, 10000, 30979, 65536):
+        parts, cols, b = m.sssp_server_shape(248, n, waiting=3)  # a backlog: the wide split
+        want = max(2, ceil_div(n, 2048))
+        assert parts <= want and parts >= 2
+        check_split(n, parts, cols)
+        assert b > 0
+    # at most half the workgroups
+    parts, cols, _ = m.sssp_server_shape(20, 65536, waiting=1)
+    assert parts == 10
+    check_split(65536, parts, cols)
+
+
+def test_latency_mode(sp):
+    m, _ = sp
+    n = 30979
+    wide = m.sssp_server_shape(248, n, waiting=1)
+    narrow = m.sssp_server_shape(248, n, waiting=0)
+    assert wide[0] == ceil_div(n, 2048) and narrow[0] == ceil_div(n, 512)
+    check_split(n, *narrow[:2])
+    # busy workgroups shrink the budget (3/4 of 248 = 186): the split is as narrow as fits
+    mid = m.sssp_server_shape(248, n, busy=150, waiting=0)
+    assert wide[0] < mid[0] <= 186 - 150 and mid[0] < narrow[0]
+    check_split(n, *mid[:2])
+    # no room left: the wide split
+    assert m.sssp_server_shape(248, n, busy=180, waiting=0)[:2] == wide[:2]
+    # switched off
+    assert m.sssp_server_shape(248, n, waiting=0, idle_gang_columns=-1)[:2] == wide[:2]
+    # explicit width
+    p, c, _ = m.sssp_server_shape(248, n, waiting=0, idle_gang_columns=1024)
+    assert p == ceil_div(n, 1024)
+    # single-workgroup queries are never split
+    assert m.sssp_server_shape(248, 3000, waiting=0)[:2] == (1, 3000)
+
+
+def test_label_correcting_gangs(sp):
+    m, _ = sp
+    # label-correcting: a gang even below single_max_n (possibly of one), lc_gang_columns wide
+    p, c, b = m.sssp_server_shape(248, 3000, method=LC, waiting=2)
+    assert p == ceil_div(3000, 1024) and b > 0
+    check_split(3000, p, c)
+    p1, c1, _ = m.sssp_server_shape(248, 700, method=LC, waiting=2)
+    assert (p1, c1) == (1, 700)
+    # latency mode narrows it to idle_gang_columns (512 by default)
+    pn, cn, _ = m.sssp_server_shape(248, 7323, method=LC, waiting=0)
+    assert pn == ceil_div(7323, 512)
+    check_split(7323, pn, cn)
+
+
+def test_arena_and_errors(sp):
+    m, sssp = sp
+    _, _, b_wide = m.sssp_server_shape(248, 20000, waiting=1)
+    _, _, b_narrow = m.sssp_server_shape(248, 20000, waiting=0)
+    assert b_narrow > b_wide > 0 and b_wide % 256 == 0
+    # a query that can never fit the arena is refused, as submit refuses it
+    with pytest.raises(sssp.SsspError) as x:
+        m.sssp_server_shape(248, 20000, waiting=1, scratch_bytes=1000)
+    assert x.value.code == sssp.SSSP_ENOMEM
+    # the latency split is skipped when its records would not fit
+    p, _, b = m.sssp_server_shape(248, 20000, waiting=0, scratch_bytes=b_wide)
+    assert p == ceil_div(20000, 2048) and b == b_wide
+    for kw in (dict(workgroups=0, n=10), dict(workgroups=8, n=0), dict(workgroups=8, n=10, method=2),
+               dict(workgroups=8, n=10, busy=-1), dict(workgroups=8, n=10, gang_columns=6)):
+        with pytest.raises(sssp.SsspError) as x:
+            m.sssp_server_shape(**kw)
+        assert x.value.code == sssp.SSSP_EINVAL
