@@ -260,9 +260,13 @@ struct sssp_server {
     // relaxations and the pred pass).  True when label-correcting is clearly
     // cheaper, which also keeps saturation throughput from dropping.
     bool lc_cheaper(const Graph& g, const Query& q) const {
+        // both methods priced at their default (wide) split: the query may have
+        // run narrower in latency mode, which costs more workgroup time
+        int32_t parts = 1, S = 0;
+        plan(g.n, kMethodDijkstra, &parts, &S);
         const double row_us = (double)g.n * g.elem / 25e3;  // bytes / (25 GB/s) in us
-        const double round_us = q.parts > 1 ? 8.0 : 5.0;
-        const double t_dij = (double)q.parts * q.rounds * round_us + (double)q.settled * row_us;
+        const double round_us = parts > 1 ? 8.0 : 5.0;
+        const double t_dij = (double)parts * q.rounds * round_us + (double)q.settled * row_us;
         int32_t parts_lc = 1, S_lc = 0;
         plan(g.n, kMethodLabelCorrecting, &parts_lc, &S_lc);
         const double t_lc = (double)parts_lc * 24 * 8.0 + 5.0 * (double)q.settled * row_us;
