@@ -423,9 +423,8 @@ def cpu_throughput(gen):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the dense-matrix Dijkstra path here runs on a "
-              "single MI355X (--gpus %d requested). Multi-GPU column sharding is described in "
-              "DESIGN.md and not implemented." % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the dense-matrix Dijkstra path runs on a single "
+              "MI355X (--gpus %d requested); column sharding across GPUs is not implemented." % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -62,7 +62,7 @@ GRID_KERNEL_FILES = ("kernels.hip", "solve.h", "lc.h", "engine.h", "sssp_interna
 
 def source_hash(files=GRID_KERNEL_FILES):
     """Short hash of the sources the whole-GPU solve is built from, plus the public
-    header and this build script's compiler flags (ties profiles to the code they measured)."""
+    header and the compiler flags set in this file (ties profiles to the code they measured)."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(files):
