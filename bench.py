@@ -100,6 +100,23 @@ def read_traffic(name):
     return float(t.group(1))
 
 
+def read_ceiling_GBps(sp, torch, buf, reps=10):
+    """Read bandwidth a plain streaming kernel (sssp_stream_read) reaches over the
+    same device buffer: the practical ceiling of a solve that streams it once.
+    Mean over `reps` launches, timed with events on the stream they run on."""
+    sp.sssp_stream_read(buf)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        sp.sssp_stream_read(buf)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    return buf.numel() * buf.element_size() / (ms * 1e-3) / 1e9
+
+
 def median_launch_ms(torch, fn, reps=7):
     fn()
     torch.cuda.synchronize()
@@ -469,6 +486,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_grid (whole-GPU persistent solve)", "kernel_ms": round(kern_ms, 4),
                 "algorithmic_bytes_per_launch": alg_bytes}
+    # the same 16 GiB read by a kernel that does nothing else: what the chip delivers
+    ceiling = read_ceiling_GBps(sp, torch, Wt)
+    roofline["read_ceiling_GBps"] = round(ceiling, 1)
+    roofline["frac_of_read_ceiling"] = round(achieved / ceiling, 4)
     round_us = [round((trace[i + 1][0] - trace[i][0]) / 1e3, 1) for i in range(len(trace) - 1)]
     large = {"n": n, "rows_relaxed": R, "rounds": rounds, "barriers": r["stats"][3],
              "round_rows": [t[1] for t in trace[:-1]], "round_us": round_us,

@@ -257,6 +257,15 @@ int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w,
 /* Largest n the one-workgroup kernel accepts. */
 int32_t sssp_single_max_n(void);
 
+/* Diagnostic: launches (asynchronously, on `stream`) a plain kernel that reads
+ * the first `bytes` of the device buffer `buf` (16-byte aligned) once, with
+ * nontemporal 16-byte loads and no other work; time it to obtain the read
+ * bandwidth the device delivers in practice, the ceiling for the
+ * row-streaming solves.  `sink` (device int32, may be NULL) exists only so the
+ * loads cannot be optimised away: at most one value is stored there, and only
+ * when the data happen to fold to a fixed pattern. */
+int sssp_stream_read(const void* buf, int64_t bytes, int32_t* sink, void* stream);
+
 /* ------------------------------------------------------------------------
  * Graphs stored as adjacency lists (CSR), for sparse graphs (the paper's m = 3n
  * family, Section IV-A) whose n x n matrix would waste memory (Section VI).

@@ -87,3 +87,26 @@ def test_hops_and_paths(sp):
                 walk.append(int(pp[walk[-1]]))
             assert path == walk[::-1] and path[0] == src
             assert sum(int(Wh[a, b]) for a, b in zip(path, path[1:])) == dd[t]
+
+
+def test_stream_read_diagnostic(sp):
+    """sssp_stream_read reads the buffer and leaves it alone: a one-word buffer whose
+    four ints fold (xor) to the kernel's fixed pattern makes it store that pattern in
+    the sink, any other data leave the sink untouched; ragged sizes run cleanly."""
+    import ctypes
+    from paper_2504_03667_amd import sssp
+    L = sssp.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for words, hit in ((1, True), (1, False), (4097, False), (1_000_003, False)):
+        buf = torch.zeros(4 * words, dtype=torch.int32, device="cuda")
+        buf[0] = 0x5EED5EED if hit else 0x5EED5EEC
+        before = buf.clone()
+        sink = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        assert L.sssp_stream_read(ctypes.c_void_p(buf.data_ptr()), 16 * words,
+                                  ctypes.c_void_p(sink.data_ptr()), stream) == 0
+        torch.cuda.synchronize()
+        assert int(sink.item()) == (0x5EED5EED if hit else -7), (words, hit)
+        assert torch.equal(buf, before)
+    big = torch.ones(3 << 20, dtype=torch.int32, device="cuda")
+    sp.sssp_stream_read(big)
+    torch.cuda.synchronize()
