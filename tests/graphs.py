@@ -77,6 +77,38 @@ def lexmin_tight_pred(W, dist):
     return np.array(pred, dtype=np.int32)
 
 
+def order_and_pred_from_distances(W, src, dist):
+    """Settle order and pred of Algorithm 1 rebuilt from the final distances alone,
+    valid with zero weights too (pure Python, tiny n).
+
+    Algorithm 1 settles the unvisited vertex of least (tentative distance, index).
+    An unvisited v has tentative distance equal to dist[v] exactly when some
+    settled u is a tight in-neighbour (dist[u] + W[u, v] == dist[v]), and more
+    otherwise; and the least tentative distance among unvisited vertices is always
+    reached by such an "available" vertex (the first unvisited vertex on a shortest
+    path to any other one is available and no farther).  So the next settled vertex
+    is the available vertex of least (dist, index).  Relaxation lowers only on
+    strict improvement, so pred[v] is the first tight in-neighbour settled before v
+    (none for the source)."""
+    n = W.shape[0]
+    settled, done, avail = [], [False] * n, {src}
+    while avail:
+        v = min(avail, key=lambda x: (int(dist[x]), x))
+        avail.discard(v)
+        done[v] = True
+        settled.append(v)
+        for x in range(n):
+            if not done[x] and x != v and W[v, x] != INF and int(dist[v]) + int(W[v, x]) == int(dist[x]):
+                avail.add(x)
+    pred = [-1] * n
+    for k, v in enumerate(settled):
+        for u in settled[:k]:
+            if W[u, v] != INF and int(dist[u]) + int(W[u, v]) == int(dist[v]):
+                pred[v] = u
+                break
+    return settled, np.array(pred, dtype=np.int32)
+
+
 def all_undirected(n, weights):
     """Every undirected graph on n vertices with each pair's weight drawn from `weights`."""
     pairs = list(itertools.combinations(range(n), 2))

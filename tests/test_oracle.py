@@ -8,7 +8,8 @@ from scipy.sparse.csgraph import csgraph_from_dense, dijkstra as scipy_dijkstra
 
 import oracle
 from tests.graphs import (INF, all_directed, all_undirected, brute_force_dist, from_edges,
-                          golden_cases, lexmin_tight_pred, random_dense)
+                          golden_cases, lexmin_tight_pred, order_and_pred_from_distances,
+                          random_dense)
 
 
 def scipy_dist(W, src):
@@ -86,6 +87,35 @@ def test_zero_weights_dist_and_certificate():
             dist, pred, _ = oracle.dijkstra(W, s)
             assert (dist.astype(np.int64) == brute_force_dist(W, s)).all()
             assert oracle.certificate(W, s, dist, pred)[0] == 0
+
+
+def _check_zero_weight_order_and_pred(W):
+    n = W.shape[0]
+    for s in range(n):
+        bf = brute_force_dist(W, s)
+        dist, pred, order, r = oracle.dijkstra(W, s, with_order=True)
+        want_order, want_pred = order_and_pred_from_distances(W, s, bf)
+        assert order[:r].tolist() == want_order, (W, s)
+        assert (pred == want_pred).all(), (W, s)
+
+
+def test_zero_weight_order_and_pred_from_distances():
+    """With zero weights, the settle order and pred are pinned by Algorithm 1's
+    selection rule restated over the brute-force distances (every vertex settled is
+    the least (dist, index) vertex with a settled tight in-neighbour; pred is the
+    first settled tight in-neighbour): exhaustively over 4-vertex undirected and
+    3-vertex directed graphs with weights {0, 1, INF}, and on random directed graphs
+    with many zero weights."""
+    for W in all_undirected(4, [0, 1, INF]):
+        _check_zero_weight_order_and_pred(W)
+    for W in all_directed(3, [0, 1, INF]):
+        _check_zero_weight_order_and_pred(W)
+    rng = np.random.default_rng(11)
+    for trial in range(150):
+        n = int(rng.integers(4, 8))
+        W = random_dense(rng, n, float(rng.uniform(0.3, 0.9)), 0, 3, directed=bool(trial % 2),
+                         zero_prob=float(rng.uniform(0.2, 0.6)))
+        _check_zero_weight_order_and_pred(W)
 
 
 def test_random_against_floyd_warshall_bellman_ford_and_scipy():
