@@ -101,9 +101,10 @@ def read_traffic(name):
 
 
 def read_ceiling_GBps(sp, torch, buf, reps=10):
-    """Read bandwidth a plain streaming kernel (sssp_stream_read) reaches over the
-    same device buffer: the practical ceiling of a solve that streams it once.
-    Mean over `reps` launches, timed with events on the stream they run on."""
+    """Read bandwidth a plain streaming kernel (sssp_stream_read: chunks claimed
+    dynamically, so no XCD waits for another) reaches over the same device buffer:
+    the practical ceiling of a solve that streams it once.  Mean over `reps`
+    launches, timed with events on the stream they run on."""
     sp.sssp_stream_read(buf)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)

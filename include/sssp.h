@@ -258,13 +258,18 @@ int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w,
 int32_t sssp_single_max_n(void);
 
 /* Diagnostic: launches (asynchronously, on `stream`) a plain kernel that reads
- * the first `bytes` of the device buffer `buf` (16-byte aligned) once, with
- * nontemporal 16-byte loads and no other work; time it to obtain the read
- * bandwidth the device delivers in practice, the ceiling for the
- * row-streaming solves.  `sink` (device int32, may be NULL) exists only so the
- * loads cannot be optimised away: at most one value is stored there, and only
- * when the data happen to fold to a fixed pattern. */
-int sssp_stream_read(const void* buf, int64_t bytes, int32_t* sink, void* stream);
+ * the first `bytes` (a positive multiple of 16) of the device buffer `buf`
+ * (16-byte aligned) exactly once with nontemporal 16-byte loads and does
+ * nothing else; time it to obtain the read bandwidth the device delivers in
+ * practice, the ceiling for the row-streaming solves.  Workgroups claim
+ * chunks of `chunk_bytes` (0: 256 KiB; else a multiple of 16 in [1 KiB,
+ * 64 MiB]) from a counter, so faster XCDs take more of them.  If `fold`
+ * (device uint32, may be NULL) is given, the xor of every 32-bit word read is
+ * xor-ed into it (zero it first to obtain the buffer's xor).  The claim
+ * counter is the library's, one per device, reset by each launch at its end:
+ * calls on one device must not overlap (issue them on one stream).
+ * SSSP_EINVAL on bad arguments, SSSP_ENOMEM / SSSP_EDEVICE on runtime errors. */
+int sssp_stream_read(const void* buf, int64_t bytes, int64_t chunk_bytes, uint32_t* fold, void* stream);
 
 /* ------------------------------------------------------------------------
  * Graphs stored as adjacency lists (CSR), for sparse graphs (the paper's m = 3n

@@ -150,7 +150,7 @@ def _declare(L):
     L.sssp_hops.argtypes = [P, P, I32, P, P]
     L.sssp_paths.argtypes = [P, P, I32, P, I32, P, P, P]
     L.sssp_single_max_n.restype = I32
-    L.sssp_stream_read.argtypes = [P, I64, P, P]
+    L.sssp_stream_read.argtypes = [P, I64, I64, P, P]
     L.sssp_edges_to_csr.argtypes = [P, P, P, I64, I32, I32, P, P, P, ctypes.POINTER(I64),
                                     ctypes.POINTER(I64), P]
     L.sssp_csr_solve.argtypes = [P, P, P, I32, I32, P, P, ctypes.POINTER(sssp_tuning), P]
@@ -279,12 +279,14 @@ def sssp_batch_max_n():
     return lib().sssp_batch_max_n()
 
 
-def sssp_stream_read(buf, nbytes=None, stream=None):
-    """sssp_stream_read: one plain read of a device tensor's bytes (a bandwidth probe)."""
+def sssp_stream_read(buf, nbytes=None, chunk_bytes=0, fold=None, stream=None):
+    """sssp_stream_read: one plain read of a device tensor's bytes (a bandwidth probe);
+    `fold`, an int32 tensor of one element on the GPU, receives the xor of the words read."""
     if not isinstance(buf, torch.Tensor) or not buf.is_cuda:
         raise TypeError("buf must be a tensor on the GPU")
     nbytes = buf.numel() * buf.element_size() if nbytes is None else nbytes
-    _check(lib().sssp_stream_read(ctypes.c_void_p(buf.data_ptr()), nbytes, None, _stream(stream)))
+    f = None if fold is None else _ptr(fold, "fold")
+    _check(lib().sssp_stream_read(ctypes.c_void_p(buf.data_ptr()), nbytes, chunk_bytes, f, _stream(stream)))
 
 
 def sssp_single_max_n():

@@ -51,8 +51,11 @@ def test_argument_validation_without_gpu(L):
     arr[0].dist, arr[0].pred = 4096, 4096
     assert L.sssp_dense_solve_batched(arr, 1, 0, None, None) == s.SSSP_EINVAL
     assert b"instance 0" in L.sssp_last_error()
-    assert L.sssp_stream_read(None, 64, None, None) == s.SSSP_EINVAL
-    assert L.sssp_stream_read(P(4100), 64, None, None) == s.SSSP_EINVAL   # not 16-byte aligned
-    assert L.sssp_stream_read(fake, 8, None, None) == s.SSSP_EINVAL       # under one 16-byte word
+    assert L.sssp_stream_read(None, 64, 0, None, None) == s.SSSP_EINVAL
+    assert L.sssp_stream_read(P(4100), 64, 0, None, None) == s.SSSP_EINVAL   # not 16-byte aligned
+    assert L.sssp_stream_read(fake, 8, 0, None, None) == s.SSSP_EINVAL       # under one 16-byte word
+    assert L.sssp_stream_read(fake, 40, 0, None, None) == s.SSSP_EINVAL      # not a multiple of 16
+    assert L.sssp_stream_read(fake, 64, 512, None, None) == s.SSSP_EINVAL    # chunk under 1 KiB
+    assert L.sssp_stream_read(fake, 64, 1032, None, None) == s.SSSP_EINVAL   # chunk not a multiple of 16
     assert L.sssp_strerror(s.SSSP_EAGAIN) == b"try again"
     assert L.sssp_version() >= 1

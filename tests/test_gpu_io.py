@@ -90,23 +90,25 @@ def test_hops_and_paths(sp):
 
 
 def test_stream_read_diagnostic(sp):
-    """sssp_stream_read reads the buffer and leaves it alone: a one-word buffer whose
-    four ints fold (xor) to the kernel's fixed pattern makes it store that pattern in
-    the sink, any other data leave the sink untouched; ragged sizes run cleanly."""
-    import ctypes
-    from paper_2504_03667_amd import sssp
-    L = sssp.lib()
-    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    for words, hit in ((1, True), (1, False), (4097, False), (1_000_003, False)):
-        buf = torch.zeros(4 * words, dtype=torch.int32, device="cuda")
-        buf[0] = 0x5EED5EED if hit else 0x5EED5EEC
-        before = buf.clone()
-        sink = torch.full((1,), -7, dtype=torch.int32, device="cuda")
-        assert L.sssp_stream_read(ctypes.c_void_p(buf.data_ptr()), 16 * words,
-                                  ctypes.c_void_p(sink.data_ptr()), stream) == 0
-        torch.cuda.synchronize()
-        assert int(sink.item()) == (0x5EED5EED if hit else -7), (words, hit)
-        assert torch.equal(buf, before)
-    big = torch.ones(3 << 20, dtype=torch.int32, device="cuda")
-    sp.sssp_stream_read(big)
+    """sssp_stream_read reads every 16-byte word of the buffer exactly once (the xor of
+    all words it reports equals the buffer's, which a skipped or repeated chunk would
+    change), for ragged sizes and several chunk sizes, three calls in a row (the
+    claim counter resets itself), and leaves the buffer unchanged."""
+    rng = np.random.default_rng(501)
+    for words, chunk in ((1, 0), (65, 1024), (4097, 0), (1_000_003, 16384), (4_194_304, 0), (3_000_001, 1 << 20)):
+        host = rng.integers(-2**31, 2**31, size=4 * words, dtype=np.int64).astype(np.int32)
+        buf = torch.from_numpy(host).cuda()
+        want = int(np.bitwise_xor.reduce(host.view(np.uint32)))
+        for rep in range(3):
+            fold = torch.zeros(1, dtype=torch.int32, device="cuda")
+            sp.sssp_stream_read(buf, chunk_bytes=chunk, fold=fold)
+            torch.cuda.synchronize()
+            assert int(fold.item()) & 0xFFFFFFFF == want, (words, chunk, rep)
+        assert np.array_equal(buf.cpu().numpy(), host)
+    # a prefix of the buffer
+    host = rng.integers(-2**31, 2**31, size=4 * 1000, dtype=np.int64).astype(np.int32)
+    buf = torch.from_numpy(host).cuda()
+    fold = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sp.sssp_stream_read(buf, nbytes=16 * 300, fold=fold)
     torch.cuda.synchronize()
+    assert int(fold.item()) & 0xFFFFFFFF == int(np.bitwise_xor.reduce(host[:1200].view(np.uint32)))
