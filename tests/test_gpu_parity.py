@@ -269,3 +269,24 @@ def test_large_workload_certificate(sp):
     assert code == 0, (oracle.CERT_CODES[code], where)
     assert np.array_equal(oracle.closed_form_pred(Wh, d), p)
     assert stats[1] == int((d != INF).sum())
+
+
+def test_beyond_32bit_element_offsets(sp):
+    """n=80000 (25.6 GB, 6.4e9 entries: element offsets past 2^32, which n=65536 never
+    reaches), whole-GPU default launch: 254 slices of 316 columns (128 lanes per row)
+    and a ragged last slice of 52.  Checked as the n=65536 case is: shortest-path
+    certificate and closed-form pred against the host matrix, for a source in the
+    first and one in the last slice."""
+    spec = gen.GraphSpec(80000, 0.05, 1, 1000, 1502)
+    Wt = gen.dense_device(spec)
+    Wh = gen.dense_host(spec)
+    assert gen.checksum_device(Wt) == gen.checksum_host(Wh)
+    for src in (0, 79999):
+        d, p, status, stats = run(sp, Wt, src, 0)
+        assert status & 3 == 0
+        code, where = oracle.certificate(Wh, src, d, p)
+        assert code == 0, (src, oracle.CERT_CODES[code], where)
+        assert np.array_equal(oracle.closed_form_pred(Wh, d), p), src
+        assert stats[1] == int((d != INF).sum())
+    del Wt
+    torch.cuda.empty_cache()
