@@ -276,7 +276,8 @@ def test_beyond_32bit_element_offsets(sp):
     reaches), whole-GPU default launch: 254 slices of 316 columns (128 lanes per row)
     and a ragged last slice of 52.  Checked as the n=65536 case is: shortest-path
     certificate and closed-form pred against the host matrix, for a source in the
-    first and one in the last slice."""
+    first and one in the last slice; the label-correcting method on the same matrix
+    must give the same output."""
     spec = gen.GraphSpec(80000, 0.05, 1, 1000, 1502)
     Wt = gen.dense_device(spec)
     Wh = gen.dense_host(spec)
@@ -288,5 +289,8 @@ def test_beyond_32bit_element_offsets(sp):
         assert code == 0, (src, oracle.CERT_CODES[code], where)
         assert np.array_equal(oracle.closed_form_pred(Wh, d), p), src
         assert stats[1] == int((d != INF).sum())
+        dl, pl, status, _ = run(sp, Wt, src, sp.SSSP_FLAG_LABEL_CORRECTING)
+        assert status & 3 == 0
+        assert np.array_equal(dl, d) and np.array_equal(pl, p), ("label-correcting", src)
     del Wt
     torch.cuda.empty_cache()
