@@ -152,8 +152,9 @@ int32_t sssp_batch_max_n(void);
  * Creation (synchronous on `stream`) validates the instances; with
  * SSSP_FLAG_COMPACT it builds exact compact copies of the distinct matrices
  * whose weights fit (uint8 when 0 <= w <= 254, uint16 when <= 65534; the
- * all-ones code means "no edge"), which cut the bytes streamed per row 4x or
- * 2x and give identical dist/pred; it then measures candidate splits of the
+ * all-ones code means "no edge") and whose n is at most 65536 (larger ones
+ * stay int32), which cut the bytes streamed per row 4x or 2x and give
+ * identical dist/pred; it then measures candidate splits of the
  * instances into workgroups (one workgroup per instance, or gangs of
  * workgroups that share an instance's columns) unless `tuning` fixes one,
  * keeps the fastest, and captures the launch into a hipGraph.  A launch

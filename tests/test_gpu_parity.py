@@ -276,12 +276,15 @@ def test_beyond_32bit_element_offsets(sp):
     reaches), whole-GPU default launch: 254 slices of 316 columns (128 lanes per row)
     and a ragged last slice of 52.  Checked as the n=65536 case is: shortest-path
     certificate and closed-form pred against the host matrix, for a source in the
-    first and one in the last slice; the label-correcting method on the same matrix
-    must give the same output."""
+    first and one in the last slice; the label-correcting method, the batched call
+    (gangs of the batched kernel) and a plan asked for compact copies (which keeps
+    the int32 matrix above 65536 vertices and replays its captured launch) on the
+    same matrix must give the same output."""
     spec = gen.GraphSpec(80000, 0.05, 1, 1000, 1502)
     Wt = gen.dense_device(spec)
     Wh = gen.dense_host(spec)
     assert gen.checksum_device(Wt) == gen.checksum_host(Wh)
+    ref = {}
     for src in (0, 79999):
         d, p, status, stats = run(sp, Wt, src, 0)
         assert status & 3 == 0
@@ -292,5 +295,26 @@ def test_beyond_32bit_element_offsets(sp):
         dl, pl, status, _ = run(sp, Wt, src, sp.SSSP_FLAG_LABEL_CORRECTING)
         assert status & 3 == 0
         assert np.array_equal(dl, d) and np.array_equal(pl, p), ("label-correcting", src)
+        ref[src] = (d, p)
+    del Wh
+    n = spec.n
+    items = [(Wt, src, torch.full((n,), -9, dtype=torch.int32, device="cuda"),
+              torch.full((n,), -9, dtype=torch.int32, device="cuda")) for src in ref]
+    sp.sssp_dense_solve_batched(items)
+    status, _ = sp.sssp_last_status()
+    assert status & 3 == 0
+    for _, src, d, p in items:
+        assert np.array_equal(d.cpu().numpy(), ref[src][0]) and np.array_equal(p.cpu().numpy(), ref[src][1]), \
+            ("batched", src)
+        d.fill_(-9)
+        p.fill_(-9)
+    with sp.BatchPlan(items, sp.SSSP_FLAG_COMPACT) as plan:
+        assert plan.info()["compact_graphs"] == 0
+        plan.launch()
+        status, _ = plan.status()
+        assert status & 3 == 0
+        for _, src, d, p in items:
+            assert np.array_equal(d.cpu().numpy(), ref[src][0]) and np.array_equal(p.cpu().numpy(), ref[src][1]), \
+                ("compact plan", src)
     del Wt
     torch.cuda.empty_cache()
