@@ -277,9 +277,10 @@ def test_beyond_32bit_element_offsets(sp):
     and a ragged last slice of 52.  Checked as the n=65536 case is: shortest-path
     certificate and closed-form pred against the host matrix, for a source in the
     first and one in the last slice; the label-correcting method, the batched call
-    (gangs of the batched kernel) and a plan asked for compact copies (which keeps
-    the int32 matrix above 65536 vertices and replays its captured launch) on the
-    same matrix must give the same output."""
+    (gangs of the batched kernel), a plan asked for compact copies (which keeps the
+    int32 matrix above 65536 vertices and replays its captured launch) and a server
+    query (gangs of the serving kernel) on the same matrix must give the same
+    output."""
     spec = gen.GraphSpec(80000, 0.05, 1, 1000, 1502)
     Wt = gen.dense_device(spec)
     Wh = gen.dense_host(spec)
@@ -316,5 +317,18 @@ def test_beyond_32bit_element_offsets(sp):
         for _, src, d, p in items:
             assert np.array_equal(d.cpu().numpy(), ref[src][0]) and np.array_equal(p.cpu().numpy(), ref[src][1]), \
                 ("compact plan", src)
+    for _, _, d, p in items:
+        d.fill_(-9)
+        p.fill_(-9)
+    torch.cuda.synchronize()
+    with sp.Server() as srv:
+        g = srv.add_graph(Wt, sp.SSSP_FLAG_COMPACT)
+        tickets = [(src, d, p, srv.submit(g, src, d, p)) for _, src, d, p in items]
+        for src, d, p, t in tickets:
+            srv.wait(t, timeout_s=60)
+            info = srv.info(t)
+            assert info["state"] == sp.SSSP_QUERY_DONE and info["status"] & 3 == 0
+            assert np.array_equal(d.cpu().numpy(), ref[src][0]) and np.array_equal(p.cpu().numpy(), ref[src][1]), \
+                ("served", src)
     del Wt
     torch.cuda.empty_cache()
