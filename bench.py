@@ -450,12 +450,6 @@ def main():
     import paper_2504_03667_amd as sp
 
     sp.lib()
-    if args.section:
-        run = {"medium": bench_medium, "many_levels": bench_many_levels, "sparse": bench_sparse,
-               "small": bench_small, "batched": bench_batched,
-               "served": lambda sp, torch, gen: bench_served(sp, torch, gen, args)}[args.section]
-        print(json.dumps({"section": args.section, args.section: run(sp, torch, gen)}))
-        return 0
     if args.copy_calibration:
         # a copy of known size: its FETCH_SIZE / WRITE_SIZE calibrate the counters
         a = torch.empty(1 << 30, dtype=torch.int32, device="cuda")
@@ -464,6 +458,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.section:
+        run = {"medium": bench_medium, "many_levels": bench_many_levels, "sparse": bench_sparse,
+               "small": bench_small, "batched": bench_batched,
+               "served": lambda sp, torch, gen: bench_served(sp, torch, gen, args)}[args.section]
+        print(json.dumps({"section": args.section, args.section: run(sp, torch, gen)}))
+        return 0
 
     # ---- n = 65536, p = 0.5, 16 GiB: the headline -------------------------------
     wl = gen.workload_single_large()
