@@ -285,6 +285,9 @@ def test_beyond_32bit_element_offsets(sp):
     Wt = gen.dense_device(spec)
     Wh = gen.dense_host(spec)
     assert gen.checksum_device(Wt) == gen.checksum_host(Wh)
+    # min over every entry (the diagonal's 0 included), max over the finite ones
+    mn, mx = sp.sssp_dense_validate(Wt, spec.n, spec.n)
+    assert (mn, mx) == (int(Wh.min()), int(Wh[Wh != INF].max()))
     ref = {}
     for src in (0, 79999):
         d, p, status, stats = run(sp, Wt, src, 0)
