@@ -112,3 +112,23 @@ def test_stream_read_diagnostic(sp):
     sp.sssp_stream_read(buf, nbytes=16 * 300, fold=fold)
     torch.cuda.synchronize()
     assert int(fold.item()) & 0xFFFFFFFF == int(np.bitwise_xor.reduce(host[:1200].view(np.uint32)))
+
+
+def test_edges_to_dense_beyond_32bit_offsets(sp):
+    """An edge list written into a 25.6 GB matrix (n = 80000: element offsets past
+    2^32), with edges at the last row and column: the device matrix's checksum equals
+    that of the oracle's host matrix, and the last row and column match exactly."""
+    n = 80000
+    eu, ev, ew = gen.sparse_edges(n, 3 * n, 1, 1000, 1503)
+    eu = np.concatenate([eu, np.array([n - 1, 1, n - 1], np.int32)])
+    ev = np.concatenate([ev, np.array([0, n - 1, n - 2], np.int32)])
+    ew = np.concatenate([ew, np.array([5, 7, 0], np.int32)])
+    W = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    assert sp.sssp_edges_to_dense(dev(eu), dev(ev), dev(ew), n, W) == 0
+    R, bad = oracle.edges_to_dense(eu, ev, ew, n)
+    assert bad == 0
+    assert gen.checksum_device(W) == gen.checksum_host(R)
+    assert np.array_equal(W[n - 1].cpu().numpy(), R[n - 1])
+    assert np.array_equal(W[:, n - 1].cpu().numpy(), R[:, n - 1])
+    del W
+    torch.cuda.empty_cache()
