@@ -379,7 +379,6 @@ typedef struct sssp_server_stats {
 /* Host monotonic clock (ns) used for all server timestamps. */
 int64_t sssp_server_now_ns(void);
 
-/* Creates a server on the current device and launches its kernel; cfg may be NULL. */
 /* The split the server gives an n-vertex query, computed on the host (no
  * device, no server): with configuration *cfg (NULL = all defaults; filled in as
  * sssp_server_create does) on a kernel of `workgroups` workgroups, for the
@@ -387,12 +386,15 @@ int64_t sssp_server_now_ns(void);
  * workgroups already hold queries in flight and `waiting` queries are queued
  * behind it (the latency-mode split of idle_gang_columns applies only when
  * waiting == 0).  *parts: workgroups that solve it (1 = one workgroup);
- * *columns: columns per member (n for one workgroup); *scratch_bytes (may be
- * NULL): arena bytes for its exchange records.  SSSP_ENOMEM if the query could
- * never fit the arena (sssp_server_submit refuses it the same way). */
+ * *columns: columns per member (n for a Dijkstra query solved by one workgroup
+ * alone; otherwise a multiple of 4, also for a label-correcting gang of one);
+ * *scratch_bytes (may be NULL): arena bytes for its exchange records.
+ * SSSP_ENOMEM if the query could never fit the arena (sssp_server_submit
+ * refuses it the same way). */
 int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t busy,
                       int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes);
 
+/* Creates a server on the current device and launches its kernel; cfg may be NULL. */
 int sssp_server_create(const sssp_server_config* cfg, sssp_server** out);
 
 /* Registers a device-resident n x n matrix (row stride ld); the server borrows

@@ -94,3 +94,53 @@ def test_arena_and_errors(sp):
         with pytest.raises(sssp.SsspError) as x:
             m.sssp_server_shape(**kw)
         assert x.value.code == sssp.SSSP_EINVAL
+
+
+def test_random_shapes_obey_the_contract(sp):
+    """2000 random (workgroups, n, method, busy, waiting, configuration) cases: one
+    workgroup up to single_max_n for the Dijkstra rounds; otherwise column slices of
+    multiples of 4 that cover n exactly, at least two Dijkstra members and never more
+    than half the workgroups (or two) in the wide split; the latency split at least as
+    many members as the wide one, within three quarters of the workgroups minus those
+    busy when it is narrower, and never more members than slices of
+    idle_gang_columns need;
+    arena bytes a multiple of 256 that hold two record slots and two lists."""
+    import numpy as np
+    m, sssp = sp
+    rng = np.random.default_rng(1600)
+    for trial in range(2000):
+        W = int(rng.integers(1, 600))
+        n = int(rng.integers(1, 70000))
+        method = int(rng.integers(0, 2))
+        busy = int(rng.integers(0, W + 1))
+        single = int(rng.choice([256, 1024, 4096]))
+        gang = int(rng.choice([256, 512, 2048]))
+        lc_gang = int(rng.choice([256, 1024]))
+        idle = int(rng.choice([-1, 256, 512]))
+        cfg = dict(single_max_n=single, gang_columns=gang, lc_gang_columns=lc_gang, idle_gang_columns=idle)
+        wide = m.sssp_server_shape(W, n, method=method, busy=busy, waiting=1, **cfg)
+        lat = m.sssp_server_shape(W, n, method=method, busy=busy, waiting=0, **cfg)
+        for parts, cols, b in (wide, lat):
+            assert parts >= 1 and b % 256 == 0, (trial, parts, cols, b)
+            if parts == 1 and method == 0:
+                assert cols == n
+            else:  # a gang, also a label-correcting gang of one
+                assert cols % 4 == 0 and parts * cols >= n > (parts - 1) * cols, (trial, parts, cols, n)
+            if parts > 1 or method == 1:
+                entry = 8 if method == 1 else 4
+                assert b >= 2 * parts * 32 + 2 * parts * cols * entry, (trial, parts, cols, b)
+        if method == 0 and n <= single:
+            assert wide[:2] == (1, n) and lat[:2] == (1, n) and wide[2] == 0
+            continue
+        width = lc_gang if method == 1 else gang
+        if method == 0:
+            assert 2 <= wide[0] <= max(2, W // 2), (trial, W, n, wide)
+            assert wide[0] <= max(2, -(-n // width))
+        else:
+            assert wide[0] <= max(1, -(-n // width)), (trial, W, n, wide)
+        assert lat[0] >= wide[0], (trial, wide, lat)
+        if lat[0] > wide[0]:
+            assert lat[0] <= (3 * W) // 4 - busy, (trial, W, busy, wide, lat)
+            assert idle > 0 and lat[0] <= -(-n // idle), (trial, idle, n, lat)
+        if idle < 0:
+            assert lat[:2] == wide[:2]
