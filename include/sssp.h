@@ -250,8 +250,9 @@ int sssp_paths(const int32_t* pred, const int32_t* hops, int32_t n, const int32_
                const int64_t* offsets, int32_t* out, void* stream);
 
 /* Weight range of a device matrix (synchronous): *min_w over all entries, *max_finite_w
- * over entries other than INT32_MAX.  *min_w < 0 means the input violates Dijkstra's
- * precondition. */
+ * over entries other than INT32_MAX.  This checks the precondition of Dijkstra's
+ * algorithm (the 1959 method Section II names as the basis assumes non-negative
+ * weights): *min_w < 0 means the input violates it. */
 int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w, int32_t* max_finite_w,
                         void* stream);
 
@@ -274,9 +275,10 @@ int sssp_stream_read(const void* buf, int64_t bytes, int64_t chunk_bytes, uint32
 
 /* ------------------------------------------------------------------------
  * Graphs stored as adjacency lists (CSR), for sparse graphs (the paper's m = 3n
- * family, Section IV-A) whose n x n matrix would waste memory (Section VI).
- * Row u lists edges u -> col[e] with weight w[e] for row_ptr[u] <= e <
- * row_ptr[u+1] (row_ptr: n + 1 int64; col, w: int32; device pointers).  The
+ * family, Section IV-A) whose n x n matrix would waste memory (the third point
+ * of Section V, the conclusion).  Row u lists edges u -> col[e] with weight
+ * w[e] for row_ptr[u] <= e < row_ptr[u+1] (row_ptr: n + 1 int64; col, w:
+ * int32; device pointers).  The
  * graph means what the matrix built from the same edges means: G[u][v] is the
  * smallest weight of the edges u -> v; self-loops and weights outside
  * [0, INT32_MAX) play no part.

@@ -1,8 +1,9 @@
 // Graphs stored as adjacency lists (CSR): the paper's sparse family (m = 3n
 // edges, Section IV-A) without the n x n matrix whose memory the paper names as
-// its weakness (Section VI).  G[u][v] is the smallest weight of the edges
-// u -> v; self-loops and weights outside [0, INT32_MAX) play no part, exactly as
-// for a matrix built from the same edge list.
+// a weakness (the third point of Section V, the conclusion).  G[u][v] is the
+// smallest weight of the edges u -> v; self-loops and weights outside
+// [0, INT32_MAX) play no part, exactly as for a matrix built from the same edge
+// list.
 //
 // Such graphs have many distinct distances and few edges, so the solve uses the
 // label-correcting method (the paper's CUDA design, Algorithms 3 and 4, made

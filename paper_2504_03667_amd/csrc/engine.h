@@ -74,12 +74,24 @@ struct Ctl {
     uint32_t trace_m[kTraceCap];       // rows streamed in each round
 };
 
+// Stamp of exchange number b during use `epoch` of a gang's record memory.
+// Bit 63 is always set, and nothing else ever stored in record or list memory
+// has it: list entries are vertex indices below 2^31 (two per 64-bit word) or
+// (dist << 32) | vertex with dist below INT32_MAX, and a record's key (which
+// can be all ones) sits 8 bytes into its 32-byte record, while records always
+// start at 32-byte offsets of the memory they share with earlier uses.  So a
+// word left in the same memory by an earlier query or launch can never pass
+// for the stamp a member is waiting for.
+__host__ __device__ constexpr uint64_t exchange_stamp(uint32_t epoch, uint32_t b) {
+    return (1ull << 63) | ((uint64_t)(epoch & 0x7fffffffu) << 32) | b;
+}
+
 // One workgroup's contribution to a round.  Written and read only with
 // agent-scope atomic accesses, which are coherent across XCDs without cache
 // writebacks or invalidates; `stamp` is stored last and tells the readers that
 // the rest (and the workgroup's list entries) is in place.
 struct alignas(32) Pub {
-    uint64_t stamp;  // (epoch << 32) | barrier number of the exchange it belongs to
+    uint64_t stamp;  // exchange_stamp(epoch, barrier number of the exchange it belongs to)
     uint64_t key;    // (would-be local min dist << 32) | lowest vertex at that dist; kNoKey if none
     uint32_t count;  // vertices of the slice at that dist, listed in the slot's list region
     uint32_t flags;  // bit 0: a zero-weight edge from the bucket to an unvisited vertex was seen
@@ -113,7 +125,7 @@ __device__ __forceinline__ void stress_delay(uint32_t key) {
 }
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return b < a ? b : a; }
-__device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
+__host__ __device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
     return ((uint64_t)d << 32) | v;
 }
 

@@ -46,7 +46,7 @@ template <int T>
 __shared__ SharedLC<T> g_lc;
 
 // Frontier entries are (dist << 32 | vertex) in 64-bit list slots.
-__device__ __forceinline__ uint64_t lc_entry(uint32_t d, uint32_t v) { return ((uint64_t)d << 32) | v; }
+__host__ __device__ constexpr uint64_t lc_entry(uint32_t d, uint32_t v) { return ((uint64_t)d << 32) | v; }
 
 // Loads of U rows (list[i], list[i + step], ...) of one column group, widened;
 // past the end of the list the last row repeats (harmless for a minimum).
@@ -346,11 +346,10 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
     clear_merge<T>(sh.mrg, 4 * T);
     auto slot_pub = [&](uint32_t s) { return pubs + (size_t)s * nwg; };
     auto slot_list = [&](uint32_t s) { return lists + (size_t)s * nwg * S; };
-    const uint64_t ep = (uint64_t)epoch << 32;
     // the next exchange: members' records of slot (b & 1) carry stamp b + 1
     auto exchange = [&]() {
         ++b;
-        return gang_exchange<T>(slot_pub((b - 1) & 1), g, ep | b, (uint32_t)nwg, timeout);
+        return gang_exchange<T>(slot_pub((b - 1) & 1), g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
     };
 
     // sweep 1 relaxes the source's row

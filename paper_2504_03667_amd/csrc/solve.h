@@ -142,9 +142,9 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
 // stamp after it.  A reader reads a record's other fields only after seeing its
 // stamp.  Thread t < members polls record t; nothing is counted in a shared
 // word.  Gives up after `timeout` wall-clock ticks (returns false) so that a
-// gang that is not co-resident cannot hang.  stamp = (epoch << 32) | b with an
-// epoch unique to this use of the records' memory, so a record left from an
-// earlier use never matches.
+// gang that is not co-resident cannot hang.  stamp = exchange_stamp(epoch, b)
+// with an epoch unique to this use of the records' memory, so neither a record
+// nor any other word left there by an earlier use ever matches.
 template <int T>
 __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, uint32_t members, long long timeout) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -376,9 +376,8 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
     uint32_t b = b0;  // barriers passed
     publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)(b & 1) * nwg + g], &lists[((size_t)(b & 1) * nwg + g) * S], sh);
-    const uint64_t ep = (uint64_t)epoch << 32;
     ++b;
-    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
+    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
 
     bool pending = false;
     uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
@@ -413,7 +412,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
                               &lists[((size_t)ns * nwg + g) * S], sh);
                 ++b;
-                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
+                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
                 continue;
             }
             if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
@@ -471,7 +470,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         pbucket = bucket;
         pM = M;
         ++b;
-        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, ep | b, (uint32_t)nwg, timeout);
+        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
     }
     if (!ok) st.status |= kStatusTimeout;
     write_dist(cs, lo, col0, width, dist);

@@ -1,0 +1,73 @@
+// Host-only check of the exchange-record encoding (built and run by
+// tests/test_encoding.py; no kernel is launched).  A gang member waits for
+// exchange_stamp(epoch, b) in each member's record.  Record memory is reused
+// by later queries and launches without being cleared, so no word that any
+// use of that memory stores may equal a stamp: this program checks, over the
+// boundary values and random samples of every field, that stamps have bit 63
+// set while list entries and records' other words at stamp offsets do not.
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+
+#include "engine.h"
+#include "lc.h"
+#include "sssp_internal.h"
+
+using namespace sssp;
+
+static int failures = 0;
+#define CHECK(c)                                                    \
+    do {                                                            \
+        if (!(c)) {                                                 \
+            std::fprintf(stderr, "FAILED line %d: %s\n", __LINE__, #c); \
+            ++failures;                                             \
+        }                                                           \
+    } while (0)
+
+int main() {
+    std::mt19937_64 rng(2504036670ull);
+    const uint32_t epochs[] = {0u, 1u, 2u, 3u, 0x7ffffffeu, 0x7fffffffu, 0x80000000u, 0xffffffffu};
+    const uint32_t bars[] = {0u, 1u, 2u, 3u, 1000u, 0x7fffffffu, 0xffffffffu};
+    for (uint32_t e : epochs)
+        for (uint32_t b : bars) {
+            const uint64_t s = exchange_stamp(e, b);
+            CHECK(s >> 63 == 1u);
+            CHECK((uint32_t)s == b);
+        }
+    // distinct (epoch mod 2^31, b) give distinct stamps
+    CHECK(exchange_stamp(5, 1) != exchange_stamp(6, 1));
+    CHECK(exchange_stamp(5, 1) != exchange_stamp(5, 2));
+    for (int i = 0; i < 1000000; ++i) {
+        const uint32_t e = (uint32_t)rng(), b = (uint32_t)rng();
+        CHECK(exchange_stamp(e, b) >> 63 == 1u);
+        // label-correcting frontier entries: dist below INT32_MAX, vertex below 2^31
+        const uint32_t d = (uint32_t)(rng() % kInf), v = (uint32_t)(rng() & 0x7fffffffu);
+        CHECK(lc_entry(d, v) >> 63 == 0u);
+        // two int32 bucket-list entries (vertex indices) read as one 64-bit word
+        const uint64_t pair = ((uint64_t)(uint32_t)(rng() & 0x7fffffffu) << 32) | (uint32_t)(rng() & 0x7fffffffu);
+        CHECK(pair >> 63 == 0u);
+        // record keys (dist << 32 | vertex, dist up to INT32_MAX) outside their own slot
+        CHECK(make_key(d, v) >> 63 == 0u);
+        if (failures > 10) break;
+    }
+    CHECK(lc_entry(kInf - 1, 0x7fffffffu) >> 63 == 0u);
+    CHECK(make_key(kInf, 0x7fffffffu) >> 63 == 0u);
+    // the record layout the argument relies on: 32-byte records with the stamp first
+    // and the (possibly all-ones) key 8 bytes in
+    CHECK(sizeof(Pub) == 32 && alignof(Pub) == 32);
+    CHECK(offsetof(Pub, stamp) == 0);
+    CHECK(offsetof(Pub, key) == 8);
+    // arena regions of batched items and served queries are multiples of 256 bytes, so
+    // every use places its records at 32-byte offsets of the shared memory
+    for (int i = 0; i < 100000; ++i) {
+        const int32_t method = (int32_t)(rng() & 1), parts = 1 + (int32_t)(rng() % 1024),
+                      S = 4 * (1 + (int32_t)(rng() % 4096));
+        const unsigned long long bytes = item_scratch_bytes(method, parts, S, sizeof(Pub));
+        CHECK(bytes % 256 == 0);
+        if (failures > 10) break;
+    }
+    if (failures) return 1;
+    std::printf("stamp encoding ok\n");
+    return 0;
+}
