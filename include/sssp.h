@@ -118,6 +118,30 @@ int sssp_dense_solve_ex(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
                         int32_t* pred, uint32_t flags, const sssp_tuning* tuning, void* stream);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as sssp_dense_solve_ex (same kernels, same dist/pred; flags LITERAL,
+ * SINGLE, GRID; no tuning), but it allocates nothing: the library scratch of
+ * the whole-GPU kernel (control block, exchange records, bucket lists) lives
+ * in one fixed array of SSSP_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * first call on that GPU until the process ends.  n <= SSSP_NOALLOC_MAX_N
+ * (larger n: SSSP_EUNSUPPORTED, nothing launched); SSSP_FLAG_LABEL_CORRECTING
+ * is refused with SSSP_EUNSUPPORTED.  `status` (device pointer to one int32,
+ * may be NULL) receives the solve's SSSP_STATUS_* bits when it finishes, in
+ * stream order; sssp_last_status() does not see these solves.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on
+ * one GPU (other streams, other host threads, the same call issued again
+ * before the previous one finished on another stream) race and give wrong
+ * results; calls on one stream are ordered and safe.  Each call clears what
+ * must start at zero with a fill kernel, so no call depends on the previous
+ * one's leftovers.  Asynchronous, like sssp_dense_solve.
+ */
+#define SSSP_NOALLOC_SCRATCH_BYTES (4u << 20)
+#define SSSP_NOALLOC_MAX_N 262144
+int sssp_dense_solve_noalloc(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
+                             int32_t* pred, uint32_t flags, int32_t* status, void* stream);
+
+/*
  * Synchronises `stream` and reports the last solve or batch launched on it by
  * this library: *status gets SSSP_STATUS_* bits, stats (may be NULL) gets the
  * 4 SSSP_STAT_* counters.  Returns SSSP_EINVAL if nothing was launched on it.

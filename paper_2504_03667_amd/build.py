@@ -11,7 +11,8 @@ BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libsssp.so")
 HIPCC = "/opt/rocm/bin/hipcc"
 
-SOURCES = ["kernels.hip", "lc.hip", "csr.hip", "api.cpp", "server.cpp", "batch.cpp", "paths.hip", "diag.hip"]
+SOURCES = ["kernels.hip", "lc.hip", "csr.hip", "api.cpp", "server.cpp", "batch.cpp", "paths.hip", "diag.hip",
+           "noalloc.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

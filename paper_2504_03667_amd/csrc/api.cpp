@@ -162,6 +162,62 @@ int check_solve_args(const int32_t* W, int64_t ld, int32_t n, int32_t src, const
     return SSSP_OK;
 }
 
+}  // namespace
+
+// Shape of a whole-GPU solve of n vertices: nwg workgroups of S columns each
+// (S a multiple of 4, nwg * S >= n).  About 64 columns (256 B of each row) per
+// workgroup by default, as many workgroups as are co-resident; wider slices
+// when n outgrows the grid.  workgroups > 0 asks for that many; one_wg forces a
+// single workgroup (the label-correcting solve on one workgroup).
+int grid_shape(int32_t n, int workgroups, bool lc, bool one_wg, int cus, int* nwg_out, int* S_out) {
+    int per_cu = 0;
+    int want = workgroups > 0 ? workgroups : (int)std::max<int64_t>(1, ((int64_t)n + 63) / 64);
+    if (one_wg) want = 1;
+    int S = (int)(((int64_t)n + want - 1) / want);
+    S = (S + 3) & ~3;
+    if (S > max_grid_slice()) S = max_grid_slice();
+    int nwg = (int)(((int64_t)n + S - 1) / S);
+    hipError_t e = (hipError_t)(lc ? lc_occupancy(S, &per_cu) : grid_occupancy(S, &per_cu));
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    const int cap = std::min(1024, per_cu * cus);
+    if (nwg > cap) {
+        nwg = cap;
+        S = (int)(((int64_t)n + nwg - 1) / nwg);
+        S = (S + 3) & ~3;
+        if (S > max_grid_slice())
+            return fail(SSSP_EUNSUPPORTED, "n=%d needs more than %d co-resident workgroups", n, cap);
+        nwg = (int)(((int64_t)n + S - 1) / S);
+    }
+    *nwg_out = nwg;
+    *S_out = S;
+    return SSSP_OK;
+}
+
+// Compute units and wall-clock rate of the current device (cached; allocates nothing).
+int device_props(int* cus, long long* clock_khz) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceInfo di;
+    int rc = device_info(dev, di);
+    if (rc) return rc;
+    *cus = di.cus;
+    *clock_khz = di.clock_khz;
+    return SSSP_OK;
+}
+
+// The one-workgroup / whole-GPU crossover of the default solve.
+int single_max_default() { return single_crossover(); }
+
+// Argument checks shared by every dense entry point (message set on failure).
+int check_dense_args(const int32_t* W, int64_t ld, int32_t n, int32_t src, const int32_t* dist,
+                     const int32_t* pred) {
+    return check_solve_args(W, ld, n, src, dist, pred);
+}
+
+namespace {
+
 int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, int32_t* pred,
           uint32_t flags, const sssp_tuning* tuning, hipStream_t stream) {
     int rc = check_solve_args(W, ld, n, src, dist, pred);
@@ -188,26 +244,10 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         e = launch_single(a, threads, stream);
         if (e != hipSuccess) return hip_fail(e, "launch(one-workgroup solve)");
     } else {
-        int per_cu = 0;
-        // slice width: about 64 columns (256 B of each row) per workgroup by default, as
-        // many workgroups as fit; wider slices when n outgrows the grid
-        int want = tuning && tuning->workgroups ? tuning->workgroups : (int)std::max<int64_t>(1, (n + 63) / 64);
-        if (lc && (flags & SSSP_FLAG_SINGLE)) want = 1;
-        int S = (int)(((int64_t)n + want - 1) / want);
-        S = (S + 3) & ~3;
-        if (S > max_grid_slice()) S = max_grid_slice();
-        int nwg = (int)(((int64_t)n + S - 1) / S);
-        e = (hipError_t)(lc ? lc_occupancy(S, &per_cu) : grid_occupancy(S, &per_cu));
-        if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-        const int cap = std::min(1024, per_cu * di.cus);
-        if (nwg > cap) {
-            nwg = cap;
-            S = (int)(((int64_t)n + nwg - 1) / nwg);
-            S = (S + 3) & ~3;
-            if (S > max_grid_slice())
-                return fail(SSSP_EUNSUPPORTED, "n=%d needs more than %d co-resident workgroups", n, cap);
-            nwg = (int)(((int64_t)n + S - 1) / S);
-        }
+        int nwg = 0, S = 0;
+        rc = grid_shape(n, tuning && tuning->workgroups ? tuning->workgroups : 0, lc, lc && (flags & SSSP_FLAG_SINGLE),
+                        di.cus, &nwg, &S);
+        if (rc) return rc;
         rc = ensure(sc, sc->pubs, sc->pubs_cap, 2 * (size_t)nwg, "exchange records");
         if (rc) return rc;
         if (lc) {

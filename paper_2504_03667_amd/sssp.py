@@ -129,6 +129,8 @@ def _declare(L):
     L.sssp_dense_solve.argtypes = [P, I32, I32, P, P, P]
     L.sssp_dense_solve_ex.argtypes = [P, I64, I32, I32, P, P, U32, ctypes.POINTER(sssp_tuning), P]
     L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    L.sssp_dense_solve_noalloc.argtypes = [P, I64, I32, I32, P, P, U32, P, P]
+    L.sssp_dense_solve_noalloc.restype = ctypes.c_int
     L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
                                            ctypes.POINTER(sssp_tuning), P]
     L.sssp_last_trace.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), I32,
@@ -219,6 +221,22 @@ def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroup
     return _check(lib().sssp_dense_solve_ex(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
                                             _ptr(pred, "pred"), flags,
                                             _tuning(threads, workgroups), _stream(stream)))
+
+
+SSSP_NOALLOC_SCRATCH_BYTES = 4 << 20
+SSSP_NOALLOC_MAX_N = 262144
+
+
+def sssp_dense_solve_noalloc(W, ld, n, src, dist, pred, flags=0, status=None, stream=None):
+    """sssp_dense_solve_noalloc: as sssp_dense_solve_ex with the library's scratch in a
+    fixed per-GPU array (nothing allocated); `status`, an int32 device tensor of one
+    element or None, receives the solve's status bits in stream order."""
+    avail = W.untyped_storage().nbytes() // 4 - W.storage_offset()
+    if n < 1 or avail < (n - 1) * ld + n or (W.dim() == 2 and W.stride(1) != 1):
+        raise ValueError("W is too small for n rows of stride ld, or its rows are not contiguous")
+    st = None if status is None else _ptr(status, "status")
+    return _check(lib().sssp_dense_solve_noalloc(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
+                                                 _ptr(pred, "pred"), flags, st, _stream(stream)))
 
 
 def sssp_last_status(stream=None):
