@@ -150,34 +150,6 @@ def test_validate_and_compact_boundaries(sp):
         assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr)
 
 
-def test_batched_workload_plan(sp):
-    """The batched workload (256 sources on one n=8192 graph + 64 graphs) through a compact,
-    autotuned plan; checked against the oracle on a sample of instances."""
-    wl = gen.workload_batched()
-    mats = [gen.dense_device(g) for g in wl.graphs]
-    items = []
-    for gi, src in wl.instances:
-        n = wl.graphs[gi].n
-        items.append((mats[gi], src, torch.empty(n, dtype=torch.int32, device="cuda"),
-                      torch.empty(n, dtype=torch.int32, device="cuda")))
-    with sp.BatchPlan(items, sp.SSSP_FLAG_COMPACT) as plan:
-        plan.launch()
-        status, stats = plan.status()
-        assert status & 3 == 0
-        info = plan.info()
-        assert info["compact_graphs"] == len(wl.graphs)
-    rng = np.random.default_rng(304)
-    sample = sorted(set(rng.integers(0, len(items), size=12).tolist()) | {0, len(items) - 1})
-    host = {}
-    for k in sample:
-        gi, src = wl.instances[k]
-        if gi not in host:
-            host[gi] = gen.dense_host(wl.graphs[gi])
-        dr, pr, _ = oracle.dijkstra(host[gi], src)
-        _, _, d, p = items[k]
-        assert np.array_equal(d.cpu().numpy(), dr) and np.array_equal(p.cpu().numpy(), pr), k
-
-
 def test_plans_label_correcting(sp):
     """Every instance through the label-correcting items (int32 and compact, with a
     zero-weight graph that forces the in-gang fallback), and the one-shot call."""

@@ -144,26 +144,6 @@ def test_server_errors_and_backpressure(sp):
     assert np.array_equal(outs[0][0].cpu().numpy(), dr)
 
 
-def test_server_workload_sample(sp):
-    """A sample of the served workload's graphs (n up to 32768) and queries."""
-    wl = gen.workload_serving(n_queries=64)
-    pick = sorted({q.graph for q in wl.queries})[:8]
-    host = {g: gen.dense_host(wl.graphs[g]) for g in pick}
-    dev = {g: torch.from_numpy(host[g]).cuda() for g in pick}
-    qs = [q for q in wl.queries if q.graph in pick]
-    outs = [outputs(wl.graphs[q.graph].n) for q in qs]
-    with sp.Server() as srv:
-        gids = {g: srv.add_graph(dev[g]) for g in pick}
-        jobs = [(q, d, p, srv.submit(gids[q.graph], q.src, d, p)) for q, (d, p) in zip(qs, outs)]
-        for q, d, p, t in jobs:
-            srv.wait(t, timeout_s=120)
-            W = host[q.graph]
-            dd, pp = d.cpu().numpy(), p.cpu().numpy()
-            code, where = oracle.certificate(W, q.src, dd, pp)
-            assert code == 0, (q, oracle.CERT_CODES[code], where)
-            assert np.array_equal(oracle.closed_form_pred(W, dd), pp)
-
-
 def test_server_compact_graphs(sp):
     """Graphs registered with SSSP_FLAG_COMPACT are streamed from exact 8/16-bit copies and
     give the same results as the int32 matrices."""
