@@ -20,13 +20,10 @@
 //     sweeps needs no cache writeback or invalidate;
 //   * once no dist changes, one pass over all edges sets pred[v] to the tail u
 //     of smallest (dist[u], u) among tight edges u -> v, u != v: Algorithm 1's
-//     pred unless a tight edge has weight 0.  Then, for n <= 65536, one
-//     workgroup runs Algorithm 1 literally over the lists (exact pred); for
-//     larger n, further sweeps count the zero-weight edges after the last
-//     positive one on a shortest path into each vertex, pred takes a tight edge
-//     that lowers (dist, that count), which gives a shortest-path tree, and
-//     status bit SSSP_STATUS_PRED_TIES reports that it may differ from
-//     Algorithm 1's.
+//     pred unless a tight edge has weight 0.  When one does, the order in
+//     which Algorithm 1 settles equal distances decides pred, and a pass over
+//     the vertices that tight zero-weight edges touch recovers that order
+//     exactly (zero_tie_pred below), for any n.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,7 +53,6 @@ int err(int code, const char* fmt, ...) {
 }
 
 constexpr int kCsrThreads = 256;
-constexpr int32_t kLiteralMaxN = 65536;
 
 // Control words of one CSR solve (device memory, zeroed by k_csr_init).
 struct CsrCtl {
@@ -64,11 +60,26 @@ struct CsrCtl {
     uint32_t pad0[31];
     uint64_t gen;  // (last completed barrier << 32) | the value it hands over
     uint32_t pad1[30];
-    uint32_t count[3];   // frontier list sizes of the distance sweeps
-    uint32_t hcount[3];  // frontier list sizes of the zero-hop sweeps
-    uint32_t zero;       // a tight zero-weight edge was seen
-    uint32_t neg;        // a negative weight was seen
+    uint32_t count[3];    // frontier list sizes of the distance sweeps
+    uint32_t zero;        // a tight zero-weight edge was seen
+    uint32_t neg;         // a negative weight was seen
+    uint32_t nlev;        // zero_tie_pred: levels holding non-plain vertices
+    uint32_t next_level;  // zero_tie_pred: levels claimed by workgroups
     uint32_t pad2[24];
+};
+
+// Scratch of zero_tie_pred (device memory; n = vertices, H = 2^hbits >= 2n).
+struct ZeroTie {
+    uint32_t* flags;   // per vertex: kNonPlain | kSeed | kAvail | kDone
+    uint32_t* lev;     // per non-plain vertex: the number of its level
+    uint32_t* seg;     // the non-plain vertices, grouped by level
+    uint32_t* cnt;     // per level: its non-plain vertices
+    uint32_t* off;     // per level: where its group starts in seg
+    uint32_t* fill;    // per level: vertices placed in its group so far
+    uint32_t* md;      // per vertex: smallest dist of a tail of a tight edge into it
+    uint64_t* ht_key;  // open-addressing table of the levels' distances (H entries)
+    uint32_t* ht_lvl;  // level number of each occupied table entry
+    uint32_t hbits;
 };
 
 __device__ __forceinline__ bool edge_ok(int32_t u, int32_t v, int32_t w, int32_t n) {
@@ -202,7 +213,7 @@ __global__ void k_csr_sort_rows(const int64_t* __restrict__ row_ptr, int32_t n, 
 // ---------------------------------------------------------------------------
 // Solve.
 //
-// Labels: a running value (dist, or the zero-hop count) and the sweep that last
+// Labels: a running value (dist) and the sweep that last
 // lowered it, packed as (value << 32) | sweep into one 64-bit word.  Sweep
 // numbers grow, so an atomic minimum with (c << 32) | k lowers the value
 // exactly when c is smaller (a tie keeps the older word), and the word it
@@ -213,23 +224,21 @@ __global__ void k_csr_sort_rows(const int64_t* __restrict__ row_ptr, int32_t n, 
 __device__ __forceinline__ uint32_t label_value(uint64_t x) { return (uint32_t)(x >> 32); }
 
 __global__ void k_csr_init(int32_t n, int32_t src, uint64_t* __restrict__ lab, uint64_t* __restrict__ pkey,
-                           uint64_t* __restrict__ hop, uint32_t* __restrict__ lists, CsrCtl* __restrict__ cc) {
+                           uint32_t* __restrict__ lists, CsrCtl* __restrict__ cc) {
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t v = gtid; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         lab[v] = v == src ? 0ull : (uint64_t)kInf << 32;
         pkey[v] = kNoKey;
-        hop[v] = (uint64_t)kInf << 32;
     }
     if (gtid == 0) {
         lists[0] = (uint32_t)src;
         cc->bar = 0;
         cc->gen = 0ull;
-        for (int i = 0; i < 3; ++i) {
-            cc->count[i] = i == 0 ? 1u : 0u;
-            cc->hcount[i] = 0;
-        }
+        for (int i = 0; i < 3; ++i) cc->count[i] = i == 0 ? 1u : 0u;
         cc->zero = 0;
         cc->neg = 0;
+        cc->nlev = 0;
+        cc->next_level = 0;
     }
 }
 
@@ -279,45 +288,10 @@ __device__ __forceinline__ bool csr_barrier(CsrCtl* cc, uint32_t b, uint32_t nwg
     return ok;
 }
 
-// Algorithm 1 over the lists, one workgroup: the exact pred when tight
-// zero-weight edges make the closed form unusable.  cand holds dist, visited
-// the settled flags (n words each, workgroup-private).
-template <int T>
-__device__ void csr_literal(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                            const int32_t* __restrict__ w, int32_t n, int32_t src, uint32_t* __restrict__ cand,
-                            uint32_t* __restrict__ visited, int32_t* __restrict__ pred, Red<T>& red,
-                            unsigned long long& rows) {
-    for (int32_t v = threadIdx.x; v < n; v += T) {
-        cand[v] = v == src ? 0u : kInf;
-        visited[v] = 0;
-        pred[v] = -1;
-    }
-    __syncthreads();
-    for (;;) {
-        uint64_t key = kNoKey;
-        for (int32_t v = threadIdx.x; v < n; v += T)
-            if (!visited[v]) key = umin64(key, make_key(cand[v], (uint32_t)v));
-        uint32_t none = 0;
-        block_min_or<T>(key, none, red);
-        const uint32_t du = (uint32_t)(key >> 32);
-        if (key == kNoKey || du >= kInf) break;
-        const int32_t u = (int32_t)(uint32_t)key;
-        if (threadIdx.x == 0) {
-            visited[u] = 1;
-            ++rows;
-            // the edges of u in list order; strict '<' keeps a repeated pair's smallest weight
-            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-                const int32_t v = col[e], wt = w[e];
-                if (!edge_ok(u, v, wt, n) || visited[v]) continue;
-                const uint32_t c = du + (uint32_t)wt;
-                if (c < cand[v]) {
-                    cand[v] = c;
-                    pred[v] = u;
-                }
-            }
-        }
-        __syncthreads();
-    }
+// Does tail u (dist du) reach head v (dist dv) over an edge of weight wt on a
+// shortest path?  Both finite, du + wt == dv (both below 2^31: no wrap).
+__device__ __forceinline__ bool tight(uint32_t du, uint32_t dv, int32_t wt) {
+    return du < kInf && dv < kInf && du + (uint32_t)wt == dv;
 }
 
 // Frontier sweeps over three rotating lists whose sizes are count[0..2]; the
@@ -455,13 +429,223 @@ __device__ __forceinline__ void for_edges(const int64_t* __restrict__ row_ptr, c
     }
 }
 
+// pred when tight zero-weight edges exist, from the exact distances alone
+// (every workgroup of the grid calls it; b counts the grid barriers).
+//
+// Algorithm 1 settles vertices in order of distance, and within one distance
+// (a level) it settles the lowest-index vertex whose dist already equals that
+// distance: the seeds (the source, and heads of tight edges of positive weight,
+// whose tails lie in lower levels) from the start, and the heads of tight
+// zero-weight edges once their tail has settled.  pred[v] is the tail of the
+// tight edge into v that settled first.  Vertices touched by no tight
+// zero-weight edge inside their level ("plain") are seeds that make nothing
+// available, so only the others ("non-plain") need a sequential pass, one
+// level per workgroup: it settles them one at a time as Algorithm 1 would,
+// y_1, y_2, ..., and a plain vertex p settles before y_i exactly when
+// p < max(y_1 .. y_i).  Hence within a level the settle order is the order of
+// the 64-bit keys p << 32 for plain p and (max(y_1 .. y_i) << 32) | i for y_i,
+// and pred[v] is the tail u of smallest (dist[u], key[u]) over tight edges
+// u -> v, u != v: found by a minimum of dist[u], then of key[u] among those
+// tails, then the tail whose key won.  The non-plain vertices are grouped by
+// level through an open-addressing table of the levels' distances.
+constexpr uint32_t kNonPlain = 1u, kSeed = 2u, kAvail = 4u, kDone = 8u;
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint32_t level_slot(uint32_t d, uint32_t hbits) {
+    return (d * 2654435761u) >> (32 - hbits);
+}
+
+template <int T>
+__device__ bool zero_tie_pred(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                              const int32_t* __restrict__ w, int32_t n, int32_t src, const uint64_t* __restrict__ lab,
+                              uint64_t* __restrict__ rk, uint64_t* __restrict__ pk, const ZeroTie& zt, CsrCtl* cc,
+                              uint32_t& b, long long timeout, int32_t* __restrict__ dist,
+                              int32_t* __restrict__ pred, Red<T>& red) {
+    __shared__ uint32_t claim;
+    const uint32_t nwg = gridDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * T + threadIdx.x;
+    const int64_t gsz = (int64_t)nwg * T;
+    const uint32_t hmask = (uint32_t)((1ull << zt.hbits) - 1ull);
+    auto D = [&](int64_t v) { return label_value(ld_agent(&lab[v])); };
+    auto set_flag = [&](int64_t v, uint32_t f) {
+        __hip_atomic_fetch_or(&zt.flags[v], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // every vertex starts plain with its own index as settle key; the table starts empty
+    for (int64_t v = gtid; v < n; v += gsz) {
+        st_agent(&zt.flags[v], v == src ? kSeed : 0u);
+        st_agent(&zt.cnt[v], 0u);
+        st_agent(&zt.fill[v], 0u);
+        st_agent(&zt.md[v], kInf);
+        st_agent(&rk[v], (uint64_t)v << 32);
+        st_agent(&pk[v], kNoKey);
+    }
+    for (int64_t h = gtid; h <= (int64_t)hmask; h += gsz) st_agent(&zt.ht_key[h], kEmpty);
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // tight zero-weight edges make both ends non-plain; positive ones make the head a seed
+    for (int64_t u = gtid; u < n; u += gsz) {
+        const uint32_t du = D(u);
+        if (du >= kInf) continue;
+        for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+            uint32_t dv[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) dv[j] = eok[j] ? D(v[j]) : kInf;
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                if (!tight(du, dv[j], wt[j])) continue;
+                if (wt[j] == 0) {
+                    set_flag(u, kNonPlain);
+                    set_flag(v[j], kNonPlain);
+                } else {
+                    set_flag(v[j], kSeed);
+                }
+            }
+        });
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // the distance of every non-plain vertex enters the table (one entry per level)
+    for (int64_t v = gtid; v < n; v += gsz) {
+        if (!(ld_agent(&zt.flags[v]) & kNonPlain)) continue;
+        const uint64_t d = D(v);
+        for (uint32_t h = level_slot((uint32_t)d, zt.hbits);; h = (h + 1) & hmask) {
+            uint64_t expect = kEmpty;
+            if (__hip_atomic_compare_exchange_strong(&zt.ht_key[h], &expect, d, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) ||
+                expect == d)
+                break;
+        }
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // number the levels
+    for (int64_t h = gtid; h <= (int64_t)hmask; h += gsz)
+        if (ld_agent(&zt.ht_key[h]) != kEmpty)
+            st_agent(&zt.ht_lvl[h], __hip_atomic_fetch_add(&cc->nlev, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // each non-plain vertex finds its level and counts itself in
+    for (int64_t v = gtid; v < n; v += gsz) {
+        if (!(ld_agent(&zt.flags[v]) & kNonPlain)) continue;
+        const uint64_t d = D(v);
+        uint32_t h = level_slot((uint32_t)d, zt.hbits);
+        while (ld_agent(&zt.ht_key[h]) != d) h = (h + 1) & hmask;
+        const uint32_t L = ld_agent(&zt.ht_lvl[h]);
+        st_agent(&zt.lev[v], L);
+        __hip_atomic_fetch_add(&zt.cnt[L], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    const uint32_t nl = ld_agent(&cc->nlev);
+    // where each level's group starts: an exclusive scan of the counts, by workgroup 0
+    if (blockIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t base = 0; base < nl; base += T) {
+            const uint32_t i = base + threadIdx.x;
+            const uint32_t c = i < nl ? ld_agent(&zt.cnt[i]) : 0u;
+            uint32_t total = 0;
+            const uint32_t ex = block_excl_scan<T>(c, total, red);
+            if (i < nl) st_agent(&zt.off[i], run + ex);
+            run += total;
+        }
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // place each non-plain vertex in its level's group
+    for (int64_t v = gtid; v < n; v += gsz) {
+        if (!(ld_agent(&zt.flags[v]) & kNonPlain)) continue;
+        const uint32_t L = ld_agent(&zt.lev[v]);
+        const uint32_t pos = ld_agent(&zt.off[L]) +
+                             __hip_atomic_fetch_add(&zt.fill[L], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_agent(&zt.seg[pos], (uint32_t)v);
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // the sequential pass of each level, a workgroup per level: settle the
+    // lowest-index available vertex, make the heads of its tight zero-weight
+    // edges available, repeat
+    for (;;) {
+        if (threadIdx.x == 0)
+            claim = __hip_atomic_fetch_add(&cc->next_level, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t L = claim;
+        __syncthreads();
+        if (L >= nl) break;
+        const uint32_t o = ld_agent(&zt.off[L]), cntL = ld_agent(&zt.cnt[L]);
+        uint32_t pm = 0, step = 0;
+        for (;;) {
+            uint64_t best = kNoKey;
+            for (uint32_t i = threadIdx.x; i < cntL; i += T) {
+                const uint32_t v = ld_agent(&zt.seg[o + i]);
+                const uint32_t f = ld_agent(&zt.flags[v]);
+                if ((f & (kSeed | kAvail)) && !(f & kDone)) best = umin64(best, v);
+            }
+            uint32_t none = 0;
+            block_min_or<T>(best, none, red);
+            if (best == kNoKey) break;
+            const uint32_t x = (uint32_t)best;
+            pm = max(pm, x);
+            ++step;
+            if (threadIdx.x == 0) {
+                set_flag(x, kDone);
+                st_agent(&rk[x], ((uint64_t)pm << 32) | step);
+            }
+            const uint32_t dx = D(x);
+            for (int64_t e = row_ptr[x] + threadIdx.x; e < row_ptr[x + 1]; e += T) {
+                const int32_t y = col[e];
+                if (w[e] == 0 && edge_ok((int32_t)x, y, 0, n) && D(y) == dx) set_flag(y, kAvail);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // the smallest tail dist of a tight edge into each vertex ...
+    for (int64_t u = gtid; u < n; u += gsz) {
+        const uint32_t du = D(u);
+        if (du >= kInf) continue;
+        for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (eok[j] && v[j] != src && tight(du, D(v[j]), wt[j]))
+                    __hip_atomic_fetch_min(&zt.md[v[j]], du, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        });
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // ... the smallest settle key among those tails ...
+    for (int64_t u = gtid; u < n; u += gsz) {
+        const uint32_t du = D(u);
+        if (du >= kInf) continue;
+        const uint64_t ku = ld_agent(&rk[u]);
+        for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (eok[j] && v[j] != src && tight(du, D(v[j]), wt[j]) && ld_agent(&zt.md[v[j]]) == du)
+                    __hip_atomic_fetch_min(&pk[v[j]], ku, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        });
+    }
+    if (!csr_barrier(cc, ++b, nwg, timeout)) return false;
+    // ... and the tail whose key won is pred (one tail per vertex: keys differ within
+    // a level); vertices without such a tail (the source, unreachable ones) get -1
+    for (int64_t u = gtid; u < n; u += gsz) {
+        const uint32_t du = D(u);
+        if (du < kInf) {
+            const uint64_t ku = ld_agent(&rk[u]);
+            for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    if (eok[j] && v[j] != src && tight(du, D(v[j]), wt[j]) && ld_agent(&zt.md[v[j]]) == du &&
+                        ld_agent(&pk[v[j]]) == ku)
+                        pred[v[j]] = (int32_t)u;
+            });
+        }
+        dist[u] = (int32_t)du;
+        if (u == src || du >= kInf || ld_agent(&pk[u]) == kNoKey) pred[u] = -1;
+    }
+    return true;
+}
+
 template <int T>
 __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                               const int32_t* __restrict__ w, int32_t n, int32_t src,
                                               int32_t* __restrict__ dist, int32_t* __restrict__ pred,
                                               uint64_t* __restrict__ lab, uint64_t* __restrict__ pkey,
-                                              uint64_t* __restrict__ hop, uint32_t* __restrict__ lists,
-                                              CsrCtl* __restrict__ cc, long long timeout, Ctl* __restrict__ ctl) {
+                                              uint64_t* __restrict__ rk, uint32_t* __restrict__ lists,
+                                              CsrCtl* __restrict__ cc, ZeroTie zt, long long timeout,
+                                              Ctl* __restrict__ ctl) {
     __shared__ Red<T> red;
     const uint32_t nwg = gridDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * T + threadIdx.x;
@@ -507,91 +691,10 @@ __global__ __launch_bounds__(T) void k_csr_lc(const int64_t* __restrict__ row_pt
     }
     uint32_t status = ok ? 0u : kStatusTimeout;
     const uint32_t Z = ok ? ld_agent(&cc->zero) : 0u;
-    if (ok && Z && n <= kLiteralMaxN) {
-        // tight zero-weight edges: Algorithm 1 literally, by workgroup 0 alone, in
-        // the memory of the hop labels (unused on this path)
-        if (blockIdx.x != 0) return;
-        uint32_t* cand = reinterpret_cast<uint32_t*>(hop);
-        csr_literal<T>(row_ptr, col, w, n, src, cand, cand + n, pred, red, rows);
-        for (int32_t v = threadIdx.x; v < n; v += T) dist[v] = (int32_t)cand[v];
-        status |= kStatusZeroFallback;
-    } else if (ok && Z) {
-        // Tight zero-weight edges on a graph too large for the literal pass: equal
-        // distances can now point at each other, so the pred of smallest
-        // (dist[u], u) may close a cycle.  hop[v] = fewest tight zero-weight edges
-        // after the last positive-weight edge of a shortest path into v (0 for the
-        // source and for heads of tight positive edges); pred then takes a tight
-        // positive edge, or a tight zero-weight edge from hop[v] - 1, of smallest
-        // (dist[u], u): a shortest-path tree, though not always Algorithm 1's.
-        auto seed = [&](int32_t v) {  // hop[v] = 0; the first to set it appends v
-            if (label_value(__hip_atomic_fetch_min(&hop[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u) {
-                const uint32_t pos =
-                    __hip_atomic_fetch_add(&cc->hcount[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                st_agent(&lists[pos], (uint32_t)v);
-            }
-        };
-        if (gtid == 0) seed(src);
-        for (int64_t u = gtid; u < n; u += gsz) {
-            st_agent(&pkey[u], kNoKey);
-            const uint32_t du = label_value(ld_agent(&lab[u]));
-            if (du >= kInf) continue;
-            for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
-                uint32_t dv[kBatch];
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j)
-                    dv[j] = (eok[j] && wt[j] != 0) ? label_value(ld_agent(&lab[v[j]])) : kInf;
-#pragma unroll
-                for (int j = 0; j < kBatch; ++j)
-                    if (dv[j] < kInf && du + (uint32_t)wt[j] == dv[j]) seed(v[j]);
-            });
-        }
-        uint32_t F0 = 0;
-        ok = csr_barrier(cc, ++b, nwg, timeout, &cc->hcount[0], &F0);
-        unsigned long long hs = 0, hr = 0;
-        if (ok)
-            ok = frontier_sweeps(
-                cc->hcount, lists, hop, row_ptr, col, w, n, cc, b, timeout, F0, hs, hr,
-                [&](int32_t u) { return make_key(label_value(ld_agent(&lab[u])), label_value(ld_agent(&hop[u]))); },
-                [&](uint64_t t, int32_t u, int32_t v, int32_t wt, uint32_t& c) {
-                    if (wt != 0 || !edge_ok(u, v, 0, n) || label_value(ld_agent(&lab[v])) != (uint32_t)(t >> 32))
-                        return false;
-                    c = (uint32_t)t + 1u;
-                    return true;
-                });
-        if (ok) {
-            for (int64_t u = gtid; u < n; u += gsz) {
-                const uint32_t du = label_value(ld_agent(&lab[u]));
-                if (du >= kInf) continue;
-                const uint32_t hu = label_value(ld_agent(&hop[u]));
-                for_edges(row_ptr, col, w, n, (int32_t)u, [&](const int32_t* v, const int32_t* wt, const bool* eok) {
-                    uint32_t dv[kBatch], hv[kBatch];
-#pragma unroll
-                    for (int j = 0; j < kBatch; ++j) {
-                        dv[j] = eok[j] ? label_value(ld_agent(&lab[v[j]])) : kInf;
-                        hv[j] = (eok[j] && wt[j] == 0) ? label_value(ld_agent(&hop[v[j]])) : 0u;
-                    }
-#pragma unroll
-                    for (int j = 0; j < kBatch; ++j) {
-                        if (dv[j] >= kInf || du + (uint32_t)wt[j] != dv[j]) continue;
-                        if (wt[j] == 0 && hu + 1u != hv[j]) continue;
-                        __hip_atomic_fetch_min(&pkey[v[j]], make_key(du, (uint32_t)u), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                });
-            }
-            ok = csr_barrier(cc, ++b, nwg, timeout);
-        }
-        if (ok) {
-            for (int64_t v = gtid; v < n; v += gsz) {
-                const uint32_t d = label_value(ld_agent(&lab[v]));
-                const uint64_t kk = ld_agent(&pkey[v]);
-                dist[v] = (int32_t)d;
-                pred[v] = (v == src || d >= kInf || kk == kNoKey) ? -1 : (int32_t)(uint32_t)kk;
-            }
-            status |= SSSP_STATUS_PRED_TIES;
-        } else {
-            status |= kStatusTimeout;
-        }
+    if (ok && Z) {
+        // tight zero-weight edges: the settle order of equal distances decides pred
+        ok = zero_tie_pred<T>(row_ptr, col, w, n, src, lab, rk, pkey, zt, cc, b, timeout, dist, pred, red);
+        status |= ok ? kStatusZeroFallback : kStatusTimeout;
     } else if (ok) {
         for (int64_t v = gtid; v < n; v += gsz) {
             const uint32_t d = label_value(ld_agent(&lab[v]));
@@ -721,30 +824,46 @@ int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w,
     if (rc) return rc;
     int nwg = 0;
     if ((rc = csr_grid(n, tuning, cus, &nwg, nullptr))) return rc;
-    // scratch: dist labels, pred keys, hop labels (n x 8 B each), 3 frontier lists (3n words), control
+    // scratch: dist labels, pred keys, settle keys (n x 8 B each), 3 frontier lists
+    // (3n words), control, and the tables of the zero-weight tie pass (7n words,
+    // 12 B per entry of a table of the smallest power of two >= 2n entries)
     const size_t words = (size_t)n;
-    const size_t bytes = 3 * words * 8 + 3 * words * 4 + sizeof(CsrCtl) + 256;
+    uint32_t hbits = 1;
+    while ((1ull << hbits) < 2ull * words) ++hbits;
+    const size_t H = (size_t)1 << hbits;
+    const size_t bytes = 3 * words * 8 + 3 * words * 4 + sizeof(CsrCtl) + 256 + H * 8 + 7 * words * 4 + H * 4 + 256;
     char* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, bytes, s);
     if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
     uint64_t* lab = reinterpret_cast<uint64_t*>(buf);
     uint64_t* pkey = lab + words;
-    uint64_t* hop = pkey + words;
-    uint32_t* lists = reinterpret_cast<uint32_t*>(hop + words);
+    uint64_t* rk = pkey + words;
+    uint32_t* lists = reinterpret_cast<uint32_t*>(rk + words);
     CsrCtl* cc = reinterpret_cast<CsrCtl*>(((uintptr_t)(lists + 3 * words) + 255) & ~(uintptr_t)255);
+    ZeroTie zt;
+    zt.ht_key = reinterpret_cast<uint64_t*>(((uintptr_t)(cc + 1) + 255) & ~(uintptr_t)255);
+    zt.ht_lvl = reinterpret_cast<uint32_t*>(zt.ht_key + H);
+    zt.flags = zt.ht_lvl + H;
+    zt.lev = zt.flags + words;
+    zt.seg = zt.lev + words;
+    zt.cnt = zt.seg + words;
+    zt.off = zt.cnt + words;
+    zt.fill = zt.off + words;
+    zt.md = zt.fill + words;
+    zt.hbits = hbits;
     const unsigned ib = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, lab, pkey, hop, lists, cc);
+    hipLaunchKernelGGL(k_csr_init, dim3(ib), dim3(256), 0, s, n, src, lab, pkey, lists, cc);
     e = hipGetLastError();
     if (e == hipSuccess) {
         long long timeout = grid_barrier_ticks(khz);
         if (grid_launch_is_plain()) {
             // ordinary launch of the same grid (co-resident by its size), for profilers
             hipLaunchKernelGGL(k_csr_lc<kCsrThreads>, dim3(nwg), dim3(kCsrThreads), 0, s, row_ptr, col, w, n, src,
-                               dist, pred, lab, pkey, hop, lists, cc, timeout, ctl);
+                               dist, pred, lab, pkey, rk, lists, cc, zt, timeout, ctl);
             e = hipGetLastError();
         } else {
             void* args[] = {(void*)&row_ptr, (void*)&col, (void*)&w, &n, &src, &dist, &pred, &lab, &pkey,
-                            &hop, &lists, &cc, &timeout, &ctl};
+                            &rk, &lists, &cc, &zt, &timeout, &ctl};
             e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_csr_lc<kCsrThreads>), dim3(nwg),
                                            dim3(kCsrThreads), args, 0, s);
         }

@@ -161,20 +161,36 @@ def test_csr_isolated_source(sp):
         check(sp, g, src, g.dev_oracle_lists, tag="isolated")
 
 
-def test_csr_large_with_zero_ties_reports_them(sp):
-    """Above 65536 vertices, tight zero-weight edges are reported (PRED_TIES); dist is
-    exact and pred a valid shortest-path tree (the certificate)."""
-    rng = np.random.default_rng(921)
-    n = 70000
-    eu, ev, ew = random_edges(rng, n, 3 * n, 0, 20, zero_prob=0.1)
-    rp, col, w = oracle.edges_to_csr(eu, ev, ew, n)
-    d, p = sp.csr_solve(dev(rp), dev(col), dev(w), 0)
-    status, _ = sp.sssp_last_status()
-    d, p = d.cpu().numpy(), p.cpu().numpy()
-    assert status & 3 == 0
-    assert oracle.certificate_csr(rp, col, w, 0, d, p)[0] == 0
-    assert bool(status & sp.SSSP_STATUS_PRED_TIES) == tight_zero_edge(rp, col, w, d)
-    assert status & sp.SSSP_STATUS_PRED_TIES
+def test_csr_large_with_zero_ties(sp):
+    """Above 65536 vertices with many tight zero-weight edges (weights in [0, 20], a
+    tenth of them forced to 0), undirected and directed: dist and pred equal the
+    oracle's Algorithm 1 over the same lists, and the zero-weight pass is reported."""
+    for directed, seed in ((False, 921), (True, 924)):
+        rng = np.random.default_rng(seed)
+        n = 70000
+        eu, ev, ew = random_edges(rng, n, 3 * n, 0, 20, zero_prob=0.1)
+        rp, col, w = oracle.edges_to_csr(eu, ev, ew, n, directed)
+        print("[csr] n=%d zero weights, directed=%s" % (n, directed), flush=True)
+        d, p = sp.csr_solve(dev(rp), dev(col), dev(w), 0)
+        status, _ = sp.sssp_last_status()
+        d, p = d.cpu().numpy(), p.cpu().numpy()
+        assert status & 3 == 0
+        assert status & sp.SSSP_STATUS_ZERO_FALLBACK
+        assert tight_zero_edge(rp, col, w, d)
+        dr, pr, _ = oracle.dijkstra_csr(rp, col, w, 0)
+        bad = np.nonzero((d != dr) | (p != pr))[0]
+        assert bad.size == 0, (directed, bad[:5].tolist(), p[bad[:5]].tolist(), pr[bad[:5]].tolist())
+
+
+def test_csr_zero_weight_levels(sp):
+    """Large levels of equal distance held together by zero-weight edges (weights 0
+    or 1, half of them 0), where the settle order inside a level decides pred."""
+    for n, seed in ((3000, 925), (20000, 926)):
+        rng = np.random.default_rng(seed)
+        eu, ev, ew = random_edges(rng, n, 3 * n, 0, 1, zero_prob=0.5)
+        g = Graph(sp, eu, ev, ew, n, bool(seed % 2))
+        for src in (0, n // 2):
+            check(sp, g, src, g.dev_oracle_lists, tag="levels %d" % n)
 
 
 def test_csr_sparse_workload(sp):
