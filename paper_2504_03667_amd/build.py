@@ -61,16 +61,42 @@ def build(verbose=False):
 GRID_KERNEL_FILES = ("kernels.hip", "solve.h", "lc.h", "engine.h", "sssp_internal.h", "api.cpp")
 
 
+def code_tokens(text):
+    """C/C++ source without its comments and with runs of whitespace collapsed: what
+    the compiler sees of it (string and character literals are kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(files=GRID_KERNEL_FILES):
-    """Short hash of the sources the whole-GPU solve is built from, plus the public
-    header and the compiler flags set in this file (ties profiles to the code they measured)."""
+    """Short hash of the code (comments and layout excluded) the whole-GPU solve is
+    built from, plus the public header and the compiler flags set in this file:
+    ties profiles to the code they measured, and survives comment-only edits."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(files):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
-    with open(os.path.join(ROOT, "include", "sssp.h"), "rb") as f:
-        h.update(f.read())
+        with open(os.path.join(CSRC, name)) as f:
+            h.update(name.encode() + b"\0" + code_tokens(f.read()).encode())
+    with open(os.path.join(ROOT, "include", "sssp.h")) as f:
+        h.update(code_tokens(f.read()).encode())
     h.update(" ".join(f for f in FLAGS if os.sep not in f).encode())  # flags, not paths
     return h.hexdigest()[:16]
 

@@ -6,9 +6,9 @@
 //
 // A workgroup owns a contiguous slice of S columns (vertices) of the matrix —
 // the single-GPU form of the paper's 1-D column division (Section III-B): it
-// keeps dist[] and visited[] of those vertices in registers and writes pred[]
-// of those vertices, so every column has exactly one writer and no atomics are
-// needed on dist or pred.
+// keeps dist[], pred[] and visited[] of those vertices in registers and writes
+// dist and pred out at the end, so every column has exactly one writer and no
+// atomics are needed on dist or pred.
 //
 // Thread layout inside a workgroup of T threads.  The slice is cut into
 // NG = ceil(S/4) column groups of 4 (one 128-bit load each).  L lanes cover the
@@ -129,22 +129,40 @@ __host__ __device__ __forceinline__ uint64_t make_key(uint32_t d, uint32_t v) {
     return ((uint64_t)d << 32) | v;
 }
 
+// Lane index within the wave, recomputed where it is used: the empty asm keeps
+// the compiler from hoisting the shuffle addresses derived from it out of the
+// round loops, where they would stay live (and spill) across the row streams.
+__device__ __forceinline__ int wave_lane() {
+    int l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    asm volatile("" : "+v"(l));
+    return l;
+}
+// x of lane (lane ^ o); o < 64
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t x, int lane, int o) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ o) << 2, (int)x);
+}
+
 __device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
+    const int lane = wave_lane();
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = umin64(x, __shfl_xor(x, o, kWave));
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t y = ((uint64_t)xor_lane32((uint32_t)(x >> 32), lane, o) << 32) | xor_lane32((uint32_t)x, lane, o);
+        x = umin64(x, y);
+    }
     return x;
 }
 __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+    const int lane = wave_lane();
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, kWave);
+    for (int o = 32; o > 0; o >>= 1) x |= xor_lane32(x, lane, o);
     return x;
 }
 // inclusive prefix sum over the wave
 __device__ __forceinline__ uint32_t wave_scan32(uint32_t x) {
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = wave_lane();
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
-        uint32_t y = __shfl_up(x, (unsigned)o, kWave);
+        const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute((lane - o) << 2, (int)x);
         if (lane >= o) x += y;
     }
     return x;
@@ -177,6 +195,20 @@ __device__ __forceinline__ void block_min_or(uint64_t& key, uint32_t& flags, Red
         flags |= red.a[i];
     }
     __syncthreads();
+}
+
+// Block-wide "any": true in every thread if pred is non-zero in some thread.
+// Also a workgroup barrier.
+template <int T>
+__device__ __forceinline__ bool block_any(int pred, Red<T>& red) {
+    const bool w = __builtin_amdgcn_ballot_w64(pred != 0) != 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) red.a[threadIdx.x / kWave] = w ? 1u : 0u;
+    __syncthreads();
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < T / kWave; ++i) any |= red.a[i];
+    __syncthreads();
+    return any != 0;
 }
 
 // Block-wide exclusive prefix sum; returns this thread's offset and the total.
@@ -294,10 +326,13 @@ __device__ __forceinline__ X key_min(X a, X b) {
     return b < a ? b : a;
 }
 
-// Columns of the slice held by one thread: G groups of 4.
+// Columns of the slice held by one thread: G groups of 4.  dist and pred stay in
+// registers for the whole solve and are written out once at the end (a8), so no
+// per-column output address is kept live across the rounds.
 template <int G, typename E = int32_t>
 struct Cols {
     uint32_t dist[G][4];
+    int32_t pred[G][4];
     key_t<E> best[G][4];
     uint32_t vis;  // bit 4k+j: visited, or not a column of the slice/matrix
 };
@@ -481,7 +516,7 @@ __device__ __forceinline__ uint32_t owner_excl_scan(uint32_t x, uint32_t& total,
         uint32_t inc = 0;
         if (threadIdx.x < kWave) {
             inc = wave_scan32(x);
-            total = __shfl(inc, kWave - 1, kWave);
+            total = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
         }
         return inc - x;
     }
@@ -501,11 +536,11 @@ __device__ __forceinline__ int local_col(const Layout& lo, int k, int j) {
     return 4 * (lo.c + k * lo.L) + j;
 }
 
-// Initialise the owned columns: dist = inf (0 at the source), not visited;
-// columns past the slice/matrix are flagged visited so they never take part.
+// Initialise the owned columns: dist = inf (0 at the source), pred = -1, not
+// visited; columns past the slice/matrix are flagged visited so they never take part.
 template <int G, typename E>
 __device__ __forceinline__ void init_cols(Cols<G, E>& cs, const Layout& lo, int64_t col0, int width,
-                                          int32_t src, int32_t* __restrict__ pred) {
+                                          int32_t src) {
     cs.vis = 0;
 #pragma unroll
     for (int k = 0; k < G; ++k)
@@ -514,8 +549,8 @@ __device__ __forceinline__ void init_cols(Cols<G, E>& cs, const Layout& lo, int6
             const int v = local_col(lo, k, j);
             const bool mine = lo.r == 0 && k * lo.L + lo.c < lo.NG && v < width;
             cs.dist[k][j] = (mine && col0 + v == src) ? 0u : kInf;
+            cs.pred[k][j] = -1;
             if (!mine) cs.vis |= 1u << (4 * k + j);
-            else pred[col0 + v] = -1;
         }
     reset_best(cs);
 }
@@ -577,9 +612,7 @@ __device__ __forceinline__ uint32_t zero_hazard(const Cols<G, E>& cs, uint32_t d
 // Apply a fused round: the bucket (mask) becomes visited; every other unvisited
 // column takes its candidate if strictly smaller (pred = the candidate's row).
 template <int G, typename E>
-__device__ __forceinline__ uint32_t commit_fused(Cols<G, E>& cs, const Layout& lo, int64_t col0,
-                                                 uint32_t d, uint32_t bucket,
-                                                 int32_t* __restrict__ pred) {
+__device__ __forceinline__ uint32_t commit_fused(Cols<G, E>& cs, uint32_t d, uint32_t bucket) {
     uint32_t neg = 0;
     cs.vis |= bucket;
 #pragma unroll
@@ -590,7 +623,7 @@ __device__ __forceinline__ uint32_t commit_fused(Cols<G, E>& cs, const Layout& l
             const uint32_t c = candidate<E>(cs.best[k][j], d, neg);
             if (c < cs.dist[k][j]) {
                 cs.dist[k][j] = c;
-                pred[col0 + local_col(lo, k, j)] = (int32_t)key_row<E>(cs.best[k][j]);
+                cs.pred[k][j] = (int32_t)key_row<E>(cs.best[k][j]);
             }
         }
     reset_best(cs);
@@ -608,18 +641,29 @@ __device__ __forceinline__ uint32_t would_be(const Cols<G, E>& cs, int k, int j,
     return c < cs.dist[k][j] ? c : cs.dist[k][j];
 }
 
-// Write the owned dist values back (a8: writeback).
+// Write the owned dist and pred values out (a8: writeback): one 16-byte store
+// per column group and array where the group is whole and aligned.
 template <int G, typename E>
-__device__ __forceinline__ void write_dist(const Cols<G, E>& cs, const Layout& lo, int64_t col0, int width,
-                                           int32_t* __restrict__ dist) {
+__device__ __forceinline__ void write_out(const Cols<G, E>& cs, const Layout& lo, int64_t col0, int width,
+                                          int32_t* __restrict__ dist, int32_t* __restrict__ pred) {
     if (lo.r != 0) return;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k * lo.L + lo.c >= lo.NG) continue;
+        const int v0 = local_col(lo, k, 0);
+        int32_t* dp = dist + col0 + v0;
+        int32_t* pp = pred + col0 + v0;
+        if (v0 + 3 < width && (((uintptr_t)dp | (uintptr_t)pp) & 15u) == 0) {
+            *reinterpret_cast<v4i*>(dp) = v4i{(int)cs.dist[k][0], (int)cs.dist[k][1], (int)cs.dist[k][2],
+                                              (int)cs.dist[k][3]};
+            *reinterpret_cast<v4i*>(pp) = v4i{cs.pred[k][0], cs.pred[k][1], cs.pred[k][2], cs.pred[k][3]};
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = local_col(lo, k, j);
-            if (v < width) dist[col0 + v] = (int32_t)cs.dist[k][j];
+            for (int j = 0; j < 4; ++j)
+                if (v0 + j < width) {
+                    dp[j] = (int32_t)cs.dist[k][j];
+                    pp[j] = cs.pred[k][j];
+                }
         }
     }
 }

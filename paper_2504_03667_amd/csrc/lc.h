@@ -349,7 +349,7 @@ __device__ __forceinline__ int solve_lc(const E* __restrict__ W, int64_t ld, int
     // the next exchange: members' records of slot (b & 1) carry stamp b + 1
     auto exchange = [&]() {
         ++b;
-        return gang_exchange<T>(slot_pub((b - 1) & 1), g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
+        return gang_exchange<T>(slot_pub((b - 1) & 1), g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
     };
 
     // sweep 1 relaxes the source's row

@@ -53,7 +53,7 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
                              bool literal, SharedSolve<T>& sh, SolveStats& st, Ctl* trace) {
     const Layout lo = make_layout<T>(n);
     Cols<G, E> cs;
-    init_cols(cs, lo, 0, n, src, pred);
+    init_cols(cs, lo, 0, n, src);
     clear_merge<T>(sh.mrg, 4 * T);
     for (;;) {
         // a2/a3: argmin over unvisited vertices, lowest index on ties
@@ -115,11 +115,11 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
             }
         }
         // a5/a6: settle the bucket and relax
-        if (lo.r == 0) st.status |= commit_fused(cs, lo, 0, d, bucket, pred);
+        if (lo.r == 0) st.status |= commit_fused(cs, d, bucket);
         else reset_best(cs);
         st.settled += M;
     }
-    write_dist(cs, lo, 0, n, dist);  // a8
+    write_out(cs, lo, 0, n, dist, pred);  // a8
     if (trace && threadIdx.x == 0) {
         const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;
         trace->trace_t[nr] = wall_clock64();
@@ -133,8 +133,9 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
 // ---------------------------------------------------------------------------
 
 // Exchange number b of a gang of `members` workgroups, rank g: publishes this
-// member's record in `slot` (filled by publish()) and waits until every
-// member's record there carries the same stamp.  Records and list entries are
+// member's record in `slot` (filled before; records `stride` 64-bit words apart,
+// the stamp in the first) and waits until every member's record there carries
+// the same stamp.  Records and list entries are
 // written and read with agent-scope atomic accesses (coherent across XCDs
 // without cache writebacks or invalidates), so the only ordering needed is that
 // a member's other stores are complete before its stamp: every wave waits for
@@ -146,7 +147,8 @@ __device__ __forceinline__ void solve_single(const E* __restrict__ W, int64_t ld
 // with an epoch unique to this use of the records' memory, so neither a record
 // nor any other word left there by an earlier use ever matches.
 template <int T>
-__device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, uint32_t members, long long timeout) {
+__device__ __forceinline__ bool stamp_exchange(uint64_t* slot, size_t stride, int g, uint64_t stamp,
+                                               uint32_t members, long long timeout, Red<T>& red) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -154,7 +156,7 @@ __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, 
     if (threadIdx.x == 0) {
         stress_delay((uint32_t)(stamp ^ (stamp >> 29)));
         __builtin_amdgcn_s_waitcnt(0);
-        st_agent(&slot[g].stamp, stamp);
+        st_agent(&slot[(size_t)g * stride], stamp);
     }
     int late = 0;
     if (threadIdx.x < members) {
@@ -162,7 +164,7 @@ __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, 
         // long round do not load the memory system the others are streaming from
         const long long t0 = wall_clock64();
         unsigned naps = 1;
-        while (ld_agent(&slot[threadIdx.x].stamp) != stamp) {
+        while (ld_agent(&slot[(size_t)threadIdx.x * stride]) != stamp) {
             for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
             if (naps < 32) naps <<= 1;
             if (wall_clock64() - t0 > timeout) {
@@ -171,7 +173,14 @@ __device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, 
             }
         }
     }
-    return __syncthreads_or(late) == 0;
+    return !block_any<T>(late, red);
+}
+
+// The exchange over 32-byte Pub records (stamp first).
+template <int T>
+__device__ __forceinline__ bool gang_exchange(Pub* slot, int g, uint64_t stamp, uint32_t members, long long timeout,
+                                              Red<T>& red) {
+    return stamp_exchange<T>(&slot->stamp, sizeof(Pub) / sizeof(uint64_t), g, stamp, members, timeout, red);
 }
 
 // Thread 0 of each member calls this once when it is done with the gang's
@@ -365,7 +374,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
     const Layout lo = make_layout<T>(S);
     Cols<G, E> cs;
-    init_cols(cs, lo, col0, width, src, pred);
+    init_cols(cs, lo, col0, width, src);
     clear_merge<T>(sh.mrg, 4 * T);
 
     // initial record: the committed state (dist[src] = 0)
@@ -377,7 +386,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
     uint32_t b = b0;  // barriers passed
     publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)(b & 1) * nwg + g], &lists[((size_t)(b & 1) * nwg + g) * S], sh);
     ++b;
-    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
+    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
 
     bool pending = false;
     uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
@@ -400,7 +409,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 __syncthreads();
                 stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
                 merge_partitions<T, G>(cs, lo, sh.mrg);
-                if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, owner_bit(lo, (int64_t)pu0 - col0, width), pred);
+                if (lo.r == 0) st.status |= commit_fused(cs, pd, owner_bit(lo, (int64_t)pu0 - col0, width));
                 else reset_best(cs);
                 st.settled += 1;
 #pragma unroll
@@ -412,10 +421,10 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
                               &lists[((size_t)ns * nwg + g) * S], sh);
                 ++b;
-                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
+                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
                 continue;
             }
-            if (lo.r == 0) st.status |= commit_fused(cs, lo, col0, pd, pbucket, pred);
+            if (lo.r == 0) st.status |= commit_fused(cs, pd, pbucket);
             else reset_best(cs);
             st.settled += pM;
         }
@@ -470,10 +479,10 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         pbucket = bucket;
         pM = M;
         ++b;
-        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout);
+        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
     }
     if (!ok) st.status |= kStatusTimeout;
-    write_dist(cs, lo, col0, width, dist);
+    write_out(cs, lo, col0, width, dist, pred);
     st.barriers += b;
     if (trace && g == 0 && threadIdx.x == 0) {
         const unsigned long long nr = st.rounds < (unsigned long long)kTraceCap ? st.rounds : kTraceCap;

@@ -23,3 +23,17 @@ def test_help_lists_sections():
     assert r.returncode == 0
     for sec in ("medium", "many_levels", "sparse", "small", "batched", "served"):
         assert sec in r.stdout
+
+
+def test_source_hash_ignores_comments_only():
+    """Profiles are tied to the kernel code by a hash of its tokens: comment and
+    layout edits keep the hash, a code edit changes it."""
+    sys.path.insert(0, ROOT)
+    from paper_2504_03667_amd.build import code_tokens
+    base = "int f(int x) {\n  return x + 1; // one\n}\n/* note */ const char* s = \"a // b\";\n"
+    comment_edit = "/* header */\nint f(int x)   {\n\n  return x + 1; // one more word\n}\n const char* s = \"a // b\";"
+    code_edit = base.replace("x + 1", "x + 2")
+    literal_edit = base.replace('"a // b"', '"a // c"')
+    assert code_tokens(base) == code_tokens(comment_edit)
+    assert code_tokens(base) != code_tokens(code_edit)
+    assert code_tokens(base) != code_tokens(literal_edit)
