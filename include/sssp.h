@@ -18,12 +18,15 @@
  *          relaxation uses a strict '<'); -1 for src and unreachable vertices.
  * All buffers belong to the caller and must stay valid until the work that
  * uses them has finished on the stream.  The library owns only its internal
- * scratch (barrier words, exchange records), cached per (device, stream).
+ * scratch (barrier words, exchange records), cached per (device, stream) until
+ * sssp_stream_release / sssp_release_all.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Solves are
  * asynchronous; synchronise the stream before reading dist/pred.  Calls that
  * share a stream are ordered; solves issued on different streams use separate
- * scratch and may overlap.
+ * scratch and may overlap, except whole-GPU solves (cooperative grids that
+ * occupy every compute unit): one issued while another runs on a different
+ * stream fails to launch (SSSP_EDEVICE); issue those on one stream.
  *
  * Errors: every entry point returns SSSP_OK (0) or a negative SSSP_E* code and
  * never throws.  sssp_last_error() returns a message for the calling thread's
@@ -53,10 +56,9 @@ extern "C" {
 /* asynchronous status bits (sssp_last_status) */
 #define SSSP_STATUS_TIMEOUT 1         /* a grid barrier gave up waiting: results invalid */
 #define SSSP_STATUS_NEG_WEIGHT 2      /* a negative weight was seen: precondition violated */
-#define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps, or sent a
-                                         label-correcting solve back to the Dijkstra rounds (informational) */
-#define SSSP_STATUS_PRED_TIES 8       /* sssp_csr_solve, n > 65536, tight zero-weight edges: dist exact, pred a
-                                         valid shortest-path tree but not necessarily Algorithm 1's */
+#define SSSP_STATUS_ZERO_FALLBACK 4   /* zero-weight edges forced single-vertex steps, sent a label-correcting
+                                         solve back to the Dijkstra rounds, or made sssp_csr_solve order
+                                         equal distances by a pass over them (informational) */
 
 /* flags for sssp_dense_solve_ex / batched calls */
 #define SSSP_FLAG_LITERAL 1u  /* settle one vertex per round: Algorithm 1 exactly as printed */
@@ -283,6 +285,29 @@ int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w,
 /* Largest n the one-workgroup kernel accepts. */
 int32_t sssp_single_max_n(void);
 
+/*
+ * Library scratch.  The solve, batched and adjacency-list calls keep a small
+ * scratch block per (device, stream): a control block, exchange records and
+ * bucket lists, about 8 bytes per vertex of the largest solve issued there,
+ * plus a few counters per device for sssp_stream_read.  It is allocated on
+ * first use and grows as needed; it is released here, not at process exit
+ * (the runtime reclaims it with the process).
+ * sssp_stream_release: waits for `stream` (on the current device), frees its
+ * scratch and forgets it, so that a stream about to be destroyed leaves no
+ * entry behind; call it before hipStreamDestroy on a stream the library has
+ * used.  A later call on the stream allocates again; sssp_last_status then
+ * reports nothing launched.  SSSP_OK also when nothing was held.
+ * sssp_release_all: the same for every stream of every device, then frees the
+ * stream-read counters after a device synchronisation of each device that has
+ * them (so it also waits for other work on those devices).  Call it before
+ * unloading the library (dlclose); servers and batch plans own their memory
+ * and are released by their destroy calls, not here.
+ * sssp_scratch_bytes: device bytes of scratch currently held, all devices.
+ */
+int sssp_stream_release(void* stream);
+int sssp_release_all(void);
+int sssp_scratch_bytes(int64_t* bytes);
+
 /* Diagnostic: launches (asynchronously, on `stream`) a plain kernel that reads
  * the first `bytes` (a positive multiple of 16) of the device buffer `buf`
  * (16-byte aligned) exactly once with nontemporal 16-byte loads and does
@@ -319,14 +344,17 @@ int sssp_edges_to_csr(const int32_t* eu, const int32_t* ev, const int32_t* ew, i
                       int64_t* bad_edges, void* stream);
 
 /* Single-source solve on a CSR graph: dist and pred as Algorithm 1 computes them
- * on the equivalent matrix (Section III-A).  The label-correcting method over
- * edges (see SSSP_FLAG_LABEL_CORRECTING) on a persistent cooperative grid, the
- * closed-form pred, and for tight zero-weight edges Algorithm 1 run literally by
- * one workgroup (n <= 65536; above, SSSP_STATUS_PRED_TIES).  tuning->workgroups
- * (may be NULL) sets the grid (default about n / 256; never above 1024 nor the
- * co-resident count).  Stats: ROUNDS = sweeps, SETTLED = edge lists
- * relaxed (the sweep count may differ between runs; dist and pred do not).
- * Allocates stream-ordered scratch of about 36 n bytes.  Asynchronous. */
+ * on the equivalent matrix (Section III-A), at any n.  The label-correcting
+ * method over edges (see SSSP_FLAG_LABEL_CORRECTING) on a persistent
+ * cooperative grid, then pred from the exact distances: the tail of smallest
+ * (dist[u], u) among tight edges into v, or, when tight zero-weight edges make
+ * the order in which Algorithm 1 settles equal distances matter, the tail that
+ * order settles first, recovered by a pass over the vertices those edges touch
+ * (one workgroup per distance; SSSP_STATUS_ZERO_FALLBACK, informational).
+ * tuning->workgroups (may be NULL) sets the grid (default about n / 256; never
+ * above 1024 nor the co-resident count).  Stats: ROUNDS = sweeps, SETTLED = edge
+ * lists relaxed (the sweep count may differ between runs; dist and pred do not).
+ * Allocates stream-ordered scratch of about 100 n bytes.  Asynchronous. */
 int sssp_csr_solve(const int64_t* row_ptr, const int32_t* col, const int32_t* w, int32_t n, int32_t src,
                    int32_t* dist, int32_t* pred, const sssp_tuning* tuning, void* stream);
 
@@ -375,7 +403,10 @@ typedef struct sssp_server_config {
                                    latency when the server is not saturated; Dijkstra and
                                    label-correcting gangs alike (0 = max(256, gang_columns / 4);
                                    < 0 = off: always gang_columns / lc_gang_columns) */
-    int32_t reserved[3];
+    int32_t idle_wait_us;   /* with nothing pending or in flight, the server thread beats the heartbeat
+                               and looks for work this often (0 = 1000); above watchdog_ms the kernel
+                               leaves whenever the server is idle and is relaunched on the next query */
+    int32_t reserved[2];
 } sssp_server_config;
 
 /* query states */

@@ -162,6 +162,30 @@ int check_solve_args(const int32_t* W, int64_t ld, int32_t n, int32_t src, const
     return SSSP_OK;
 }
 
+// Device bytes held by one scratch block.
+size_t block_bytes(const Scratch& s) {
+    return (s.ctl ? ctl_size() : 0) + s.pubs_cap * sizeof(Pub) + s.lists_cap * sizeof(int32_t) +
+           s.lists64_cap * sizeof(uint64_t);
+}
+
+// Waits for the block's stream, then frees its device memory.  Caller holds g_mu.
+void free_block(Scratch& s) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != s.device) (void)hipSetDevice(s.device);
+    (void)hipStreamSynchronize(s.stream);
+    (void)hipFree(s.ctl);
+    (void)hipFree(s.pubs);
+    (void)hipFree(s.lists);
+    (void)hipFree(s.lists64);
+    s.ctl = nullptr;
+    s.pubs = nullptr;
+    s.lists = nullptr;
+    s.lists64 = nullptr;
+    s.pubs_cap = s.lists_cap = s.lists64_cap = 0;
+    if (cur >= 0 && cur != s.device) (void)hipSetDevice(cur);
+}
+
 }  // namespace
 
 // Shape of a whole-GPU solve of n vertices: nwg workgroups of S columns each
@@ -386,5 +410,39 @@ int sssp_last_trace(void* stream, int64_t* t_ns, int32_t* rows, int32_t cap, int
 
 
 int32_t sssp_single_max_n(void) { return max_single_n(); }
+
+int sssp_stream_release(void* stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = 0; i < g_scratch.size(); ++i)
+        if (g_scratch[i]->device == dev && g_scratch[i]->stream == (hipStream_t)stream) {
+            free_block(*g_scratch[i]);
+            g_scratch.erase(g_scratch.begin() + (std::ptrdiff_t)i);
+            break;
+        }
+    return SSSP_OK;
+}
+
+int sssp_release_all(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& s : g_scratch) free_block(*s);
+        g_scratch.clear();
+    }
+    return release_read_counters();
+}
+
+int sssp_scratch_bytes(int64_t* bytes) {
+    if (!bytes) return fail(SSSP_EINVAL, "bytes is NULL");
+    int64_t total = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& s : g_scratch) total += (int64_t)block_bytes(*s);
+    }
+    *bytes = total + read_counter_bytes();
+    return SSSP_OK;
+}
 
 }  // extern "C"

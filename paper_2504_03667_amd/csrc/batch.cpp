@@ -137,6 +137,23 @@ int check_all(const sssp_instance* inst, int32_t count) {
 
 namespace sssp {
 
+int matrix_range(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, int32_t* wmin, int32_t* wmax, int32_t* woff) {
+    int32_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, 3 * sizeof(int32_t));
+    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc(range): %s", hipGetErrorString(e));
+    int32_t init[3] = {0x7fffffff, (int32_t)0x80000000, 0x7fffffff}, r[3];
+    e = hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = weight_range(W, ld, n, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, d, sizeof r, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_err(e, "weight range");
+    *wmin = r[0];
+    *wmax = r[1];
+    *woff = r[2];
+    return SSSP_OK;
+}
+
 // Exact compact copy of W when every weight is >= 0 and every finite weight
 // fits below the all-ones code of uint8 (<= 254) or uint16 (<= 65534).
 // Synchronous.  out->elem == 4 (and no copy) when neither fits.
@@ -144,18 +161,12 @@ int make_compact(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, Compact
     out->data = nullptr;
     out->ld = ld;
     out->elem = 4;
-    int32_t* d = nullptr;
-    hipError_t e = hipMalloc(&d, 2 * sizeof(int32_t));
-    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc(range): %s", hipGetErrorString(e));
-    int32_t init[2] = {0x7fffffff, (int32_t)0x80000000}, r[2];
-    e = hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = weight_range(W, ld, n, d, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(r, d, sizeof r, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d);
-    if (e != hipSuccess) return hip_err(e, "weight range");
+    int32_t r[3];
+    if (int rc = matrix_range(W, ld, n, s, &r[0], &r[1], &r[2])) return rc;
     out->wmin = r[0];
     out->wmax = r[1];
+    out->woff = r[2];
+    hipError_t e;
     // compact keys carry the row in 16 bits: copies only for n <= 65536
     int elem = 4;
     if (n > 65536) elem = 4;
@@ -346,20 +357,8 @@ int sssp_dense_validate(const int32_t* W, int64_t ld, int32_t n, int32_t* min_w,
                         void* stream) {
     if (!W || !min_w || !max_finite_w) return err(SSSP_EINVAL, "null argument");
     if (n < 1 || ld < n) return err(SSSP_EINVAL, "need n >= 1 and ld >= n");
-    hipStream_t s = (hipStream_t)stream;
-    int32_t* d = nullptr;
-    hipError_t e = hipMalloc(&d, 2 * sizeof(int32_t));
-    if (e != hipSuccess) return err(SSSP_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
-    int32_t init[2] = {0x7fffffff, (int32_t)0x80000000}, r[2];
-    e = hipMemcpyAsync(d, init, sizeof init, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = weight_range(W, ld, n, d, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(r, d, sizeof r, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d);
-    if (e != hipSuccess) return hip_err(e, "weight range");
-    *min_w = r[0];
-    *max_finite_w = r[1];
-    return SSSP_OK;
+    int32_t woff = 0;
+    return matrix_range(W, ld, n, (hipStream_t)stream, min_w, max_finite_w, &woff);
 }
 
 int sssp_dense_solve_batched(const sssp_instance* inst, int32_t count, uint32_t flags, const sssp_tuning* tuning,

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_stream_read(const v4i* __restrict_
 }
 
 std::mutex g_read_mu;
-std::vector<ReadCounters*> g_read_counters;  // per device, kept until the process ends
+std::vector<ReadCounters*> g_read_counters;  // per device, kept until sssp_release_all or the process ends
 
 int read_counters(int dev, ReadCounters** out) {
     std::lock_guard<std::mutex> lk(g_read_mu);
@@ -99,6 +99,33 @@ int read_counters(int dev, ReadCounters** out) {
 }
 
 }  // namespace
+
+namespace sssp {
+
+int release_read_counters() {
+    std::lock_guard<std::mutex> lk(g_read_mu);
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (size_t d = 0; d < g_read_counters.size(); ++d) {
+        if (!g_read_counters[d]) continue;
+        // a read may still run on any stream of that device
+        if (hipSetDevice((int)d) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return set_error(SSSP_EDEVICE, "synchronising a device before freeing its read counters failed");
+        (void)hipFree(g_read_counters[d]);
+        g_read_counters[d] = nullptr;
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    return SSSP_OK;
+}
+
+int64_t read_counter_bytes() {
+    std::lock_guard<std::mutex> lk(g_read_mu);
+    int64_t b = 0;
+    for (ReadCounters* p : g_read_counters) b += p ? (int64_t)sizeof(ReadCounters) : 0;
+    return b;
+}
+
+}  // namespace sssp
 
 extern "C" int sssp_stream_read(const void* buf, int64_t bytes, int64_t chunk_bytes, uint32_t* fold,
                                 void* stream) {

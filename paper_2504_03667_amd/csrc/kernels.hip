@@ -218,30 +218,35 @@ __global__ __launch_bounds__(T) void k_batch(const BatchItem* __restrict__ items
 }
 
 // Weight range of a matrix: out[0] = min over all entries, out[1] = max over
-// entries other than INT32_MAX (no edge).  out must hold {INT32_MAX, INT32_MIN}.
+// entries other than INT32_MAX (no edge), out[2] = min over the off-diagonal
+// entries.  out must hold {INT32_MAX, INT32_MIN, INT32_MAX}.
 __global__ void k_weight_range(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t* __restrict__ out) {
-    __shared__ int32_t smin[256], smax[256];
-    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+    __shared__ int32_t smin[256], smax[256], soff[256];
+    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000, off = 0x7fffffff;
     const int64_t total = (int64_t)n * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / n, j = e - i * n;
         const int32_t w = W[i * ld + j];
         mn = min(mn, w);
         if (w != 0x7fffffff) mx = max(mx, w);
+        if (i != j) off = min(off, w);
     }
     smin[threadIdx.x] = mn;
     smax[threadIdx.x] = mx;
+    soff[threadIdx.x] = off;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + s]);
             smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + s]);
+            soff[threadIdx.x] = min(soff[threadIdx.x], soff[threadIdx.x + s]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         atomicMin(&out[0], smin[0]);
         atomicMax(&out[1], smax[0]);
+        atomicMin(&out[2], soff[0]);
     }
 }
 
@@ -434,8 +439,8 @@ int batch_occupancy(int* per_cu) {
 int max_batch_single_n() { return 4 * 4 * 1024; }
 int max_batch_slice() { return 4 * 4 * 1024; }
 
-hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out2, hipStream_t s) {
-    hipLaunchKernelGGL(k_weight_range, dim3(2048), dim3(256), 0, s, W, ld, n, d_out2);
+hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out3, hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_range, dim3(2048), dim3(256), 0, s, W, ld, n, d_out3);
     return hipGetLastError();
 }
 

@@ -132,6 +132,7 @@ int normalize(sssp_server_config& c) {
     if (c.scratch_bytes <= 0) c.scratch_bytes = 256ll << 20;
     if (c.watchdog_ms <= 0) c.watchdog_ms = 2000;
     if (c.idle_park_ms <= 0) c.idle_park_ms = 20;
+    if (c.idle_wait_us <= 0) c.idle_wait_us = 1000;
     if (c.lc_rounds == 0) c.lc_rounds = 64;
     if (c.lc_gang_columns <= 0) c.lc_gang_columns = 1024;
     c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
@@ -386,6 +387,8 @@ struct sssp_server {
                 __atomic_store_n(&ctl->park, 0u, __ATOMIC_RELEASE);
             }
             if (!pending.empty() || !running.empty()) last_busy = t;
+            if (live && !parking && !pending.empty() && running.empty() && hipStreamQuery(stream) == hipSuccess)
+                live = false;  // the kernel left (its heartbeat watchdog fired while the server was idle)
             if (!live && !parking && !pending.empty()) launch();
             if (live && !parking) admit();
             if (collect()) {
@@ -405,7 +408,7 @@ struct sssp_server {
                 if (hipStreamQuery(stream) == hipSuccess) launch();
             }
             if (running.empty() && pending.empty()) {
-                wake.wait_for(lk, std::chrono::milliseconds(1));
+                wake.wait_for(lk, std::chrono::microseconds(cfg.idle_wait_us));
             } else {
                 lk.unlock();
                 const int64_t until = now_ns() + 2000;  // poll completions every ~2 us

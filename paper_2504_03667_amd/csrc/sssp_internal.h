@@ -96,15 +96,26 @@ struct CompactCopy {
     int64_t ld = 0;        // row stride in entries
     int elem = 4;          // 1, 2, or 4 (no copy)
     int32_t wmin = 0, wmax = 0;
+    int32_t woff = 0;      // smallest off-diagonal entry
 };
 int make_compact(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, CompactCopy* out);
+// Weight range of a matrix (synchronous): min over all entries, max over finite
+// ones, min over off-diagonal ones.
+int matrix_range(const int32_t* W, int64_t ld, int32_t n, hipStream_t s, int32_t* wmin, int32_t* wmax, int32_t* woff);
 
 // Exact compact copies (int32 -> uint16 / uint8) and weight ranges.
-hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out2, hipStream_t s);
+// d_out3 (device, 3 int32): min over all entries, max over finite entries, min
+// over off-diagonal entries; initialised by the caller to {INT32_MAX, INT32_MIN, INT32_MAX}.
+hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out3, hipStream_t s);
 hipError_t compact_copy(const int32_t* W, int64_t ld, int32_t n, void* C, int64_t ldc, int elem, hipStream_t s);
 
 size_t ctl_size();
 size_t pub_size();
+
+// Per-device counters of the read-ceiling kernel (diag.hip): freed (after a
+// device synchronisation) by sssp_release_all; their device bytes.
+int release_read_counters();
+int64_t read_counter_bytes();
 
 }  // namespace sssp
 

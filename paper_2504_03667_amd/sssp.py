@@ -25,7 +25,6 @@ SSSP_EUNSUPPORTED = -7
 SSSP_STATUS_TIMEOUT = 1
 SSSP_STATUS_NEG_WEIGHT = 2
 SSSP_STATUS_ZERO_FALLBACK = 4
-SSSP_STATUS_PRED_TIES = 8
 
 SSSP_FLAG_LITERAL = 1
 SSSP_FLAG_SINGLE = 2
@@ -77,7 +76,8 @@ class sssp_server_config(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_int64), ("max_pending", ctypes.c_int64),
                 ("idle_park_ms", ctypes.c_int32), ("lc_rounds", ctypes.c_int32),
                 ("lc_gang_columns", ctypes.c_int32), ("lc_model", ctypes.c_int32),
-                ("idle_gang_columns", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("idle_gang_columns", ctypes.c_int32), ("idle_wait_us", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class sssp_query_info(ctypes.Structure):
@@ -131,6 +131,12 @@ def _declare(L):
     L.sssp_last_status.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     L.sssp_dense_solve_noalloc.argtypes = [P, I64, I32, I32, P, P, U32, P, P]
     L.sssp_dense_solve_noalloc.restype = ctypes.c_int
+    L.sssp_stream_release.argtypes = [P]
+    L.sssp_stream_release.restype = ctypes.c_int
+    L.sssp_release_all.argtypes = []
+    L.sssp_release_all.restype = ctypes.c_int
+    L.sssp_scratch_bytes.argtypes = [ctypes.POINTER(I64)]
+    L.sssp_scratch_bytes.restype = ctypes.c_int
     L.sssp_dense_solve_batched.argtypes = [ctypes.POINTER(sssp_instance), I32, U32,
                                            ctypes.POINTER(sssp_tuning), P]
     L.sssp_last_trace.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), I32,
@@ -237,6 +243,24 @@ def sssp_dense_solve_noalloc(W, ld, n, src, dist, pred, flags=0, status=None, st
     st = None if status is None else _ptr(status, "status")
     return _check(lib().sssp_dense_solve_noalloc(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
                                                  _ptr(pred, "pred"), flags, st, _stream(stream)))
+
+
+def sssp_stream_release(stream=None):
+    """Frees the library scratch held for `stream` (default: the current stream) after
+    waiting for it; a stream about to be destroyed leaves nothing behind."""
+    return _check(lib().sssp_stream_release(_stream(stream)))
+
+
+def sssp_release_all():
+    """Frees every scratch block the library holds (all streams, all devices)."""
+    return _check(lib().sssp_release_all())
+
+
+def sssp_scratch_bytes():
+    """Device bytes of library scratch currently held."""
+    b = ctypes.c_int64(0)
+    _check(lib().sssp_scratch_bytes(ctypes.byref(b)))
+    return b.value
 
 
 def sssp_last_status(stream=None):
@@ -502,7 +526,10 @@ def sssp_server_now_ns():
 def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, **cfg):
     """sssp_server_shape (host only): (parts, columns, scratch_bytes) of an n-vertex query."""
     c = sssp_server_config()
+    names = {f for f, _ in sssp_server_config._fields_} - {"reserved"}
     for k, v in cfg.items():
+        if k not in names:
+            raise TypeError("unknown server setting %r" % k)
         setattr(c, k, v)
     parts, cols, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
     _check(lib().sssp_server_shape(ctypes.byref(c), workgroups, n, method, busy, waiting, ctypes.byref(parts),
@@ -512,7 +539,10 @@ def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, **cfg):
 
 def sssp_server_create(**cfg):
     c = sssp_server_config()
+    names = {f for f, _ in sssp_server_config._fields_} - {"reserved"}
     for k, v in cfg.items():
+        if k not in names:
+            raise TypeError("unknown server setting %r" % k)
         setattr(c, k, v)
     h = ctypes.c_void_p()
     _check(lib().sssp_server_create(ctypes.byref(c), ctypes.byref(h)))

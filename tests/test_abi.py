@@ -59,3 +59,22 @@ def test_argument_validation_without_gpu(L):
     assert L.sssp_stream_read(fake, 64, 1032, None, None) == s.SSSP_EINVAL   # chunk not a multiple of 16
     assert L.sssp_strerror(s.SSSP_EAGAIN) == b"try again"
     assert L.sssp_version() >= 1
+
+
+def test_load_release_unload_twice(tmp_path):
+    """Two load / release / unload cycles of separate copies of the library: the
+    release calls succeed with nothing held, report zero scratch, and dlclose
+    returns cleanly (no kernel is launched)."""
+    import _ctypes
+    import shutil
+    import paper_2504_03667_amd.sssp as s
+    for rep in range(2):
+        path = str(tmp_path / ("libsssp_copy%d.so" % rep))
+        shutil.copy(s.SO, path)
+        L = ctypes.CDLL(path)
+        L.sssp_scratch_bytes.argtypes = [ctypes.POINTER(ctypes.c_int64)]
+        b = ctypes.c_int64(-1)
+        assert L.sssp_scratch_bytes(ctypes.byref(b)) == s.SSSP_OK and b.value == 0
+        assert L.sssp_release_all() == s.SSSP_OK
+        assert L.sssp_scratch_bytes(None) == s.SSSP_EINVAL
+        _ctypes.dlclose(L._handle)
