@@ -16,6 +16,7 @@ import gc
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -118,7 +119,7 @@ def read_ceiling_GBps(sp, torch, buf, reps=10):
     return buf.numel() * buf.element_size() / (ms * 1e-3) / 1e9
 
 
-def median_launch_ms(torch, fn, reps=7):
+def median_launch_ms(torch, fn, reps=11):
     fn()
     torch.cuda.synchronize()
     ts = []
@@ -283,6 +284,16 @@ def bench_batched(sp, torch, gen):
     res["rows_relaxed"] = bstats[1]
     for name in ("one_shot", "plan_int32", "plan_compact"):
         res[name]["speedup_vs_plain"] = round(res[name]["solves_per_s"] / plain, 2)
+    # a plan pays for its build (compact copies, autotuning, capture) over its launches:
+    # the speedup with the build spread over 100 launches, and the launches it takes
+    # until the plan (build included) has beaten solving one instance per launch
+    plain_batch_ms = len(items) / plain * 1e3
+    for name in ("plan_int32", "plan_compact"):
+        r = res[name]
+        r["speedup_vs_plain_build_over_100_launches"] = round(
+            plain_batch_ms * 100 / (r["build_ms"] + 100 * r["launch_ms"]), 2)
+        gain = plain_batch_ms - r["launch_ms"]
+        r["launches_to_repay_build"] = round(r["build_ms"] / gain, 2) if gain > 0 else None
     del mats, items
     return res
 
@@ -406,22 +417,42 @@ def bench_served(sp, torch, gen, args):
     return res
 
 
+def host_cpu():
+    """The host CPU as the process sees it: lscpu's model and topology, the cores the
+    process may run on (its affinity) and its cgroup CPU quota; usable_cores is the
+    smaller of the two, the threads the CPU baselines use."""
+    info = {"nproc": len(os.sched_getaffinity(0)), "model": "", "lscpu": {}}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "Vendor ID", "CPU family", "Model", "Socket(s)", "Core(s) per socket",
+                     "Thread(s) per core", "CPU(s)", "CPU max MHz", "L3"):
+                info["lscpu"][k] = v
+        info["model"] = info["lscpu"].get("Model name", "")
+    except (OSError, subprocess.SubprocessError):
+        pass
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(period)
+    except (OSError, ValueError):
+        pass
+    info["cgroup_cpu_quota"] = quota
+    info["usable_cores"] = max(1, min(info["nproc"], int(quota) if quota else info["nproc"]))
+    return info
+
+
 def cpu_throughput(gen):
     """Independent oracle solves spread over every host core (one solve per thread), on
     samples of the batched and served instance sets: CPU solves/s for context."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
-    # the host share of one GPU is 16 cores, whatever the machine has in total
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    model = ""
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    out = {"cores": cores, "cpu_model": model, "kind": "oracle"}
+    host = host_cpu()
+    cores = host["usable_cores"]
+    out = {"cores": cores, "cpu_model": host["model"], "host": host, "kind": "oracle"}
     for name, wl, per_core in (("batched", gen.workload_batched(), 32), ("served", gen.workload_serving(n_queries=400), 12)):
         pairs = wl.instances if wl.instances else [(q.graph, q.src) for q in wl.queries]
         rng = np.random.default_rng(7)
@@ -542,9 +573,11 @@ def main():
         t0 = time.perf_counter()
         rel = oracle.dijkstra_prefix(Wh, 0, args.cpu_iters)
         dt = time.perf_counter() - t0
+        host = host_cpu()
         cpu = {"value": n * rel / dt, "unit": "matrix entries scanned/s", "cores": 1, "kind": "oracle",
                "sample": "first %d of %d iterations of Algorithm 1 (serial C, one thread) on the "
-                         "n=65536 p=0.5 source-0 solve, %.1f s" % (args.cpu_iters, n, dt)}
+                         "n=65536 p=0.5 source-0 solve, %.1f s" % (args.cpu_iters, n, dt),
+               "cpu_model": host["model"], "nproc": host["nproc"], "cgroup_cpu_quota": host["cgroup_cpu_quota"]}
         del Wh
 
     line = {
