@@ -110,6 +110,10 @@ def test_load_use_release_unload_twice(sp):
     scratch, about 1 MB at n=65536), sssp_release_all and dlclose; the second
     cycle must not lose device memory beyond half of what a cycle held."""
     code = "ROOT = %r\n" % ROOT + textwrap.dedent(CYCLES)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    # the ordinary launch of the same whole-GPU grids: this process may hold the
+    # device's cooperative-launch resources, and a second process's cooperative
+    # launch is then refused
+    env = dict(os.environ, SSSP_GRID_LAUNCH="plain")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240, env=env)
     print(r.stdout)
     assert r.returncode == 0 and "cycles ok" in r.stdout, r.stderr[-3000:]
