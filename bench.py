@@ -272,6 +272,8 @@ def bench_batched(sp, torch, gen):
                      "identical_to_one_shot": same, "single_max_n": info["single_max_n"],
                      "gang_columns": info["gang_columns"], "candidates": info["candidates"],
                      "compact_graphs": info["compact_graphs"], "build_ms": round(info["build_ms"], 1),
+                     "group_sources": info["group_sources"], "group_columns": info["group_columns"],
+                     "group_items": info["group_items"],
                      "algorithmic_GBps": round(alg[flags] / (t * 1e-3) / 1e9, 1)}
     # plain path: one sssp_dense_solve per instance, synchronised each time
     t0 = time.perf_counter()

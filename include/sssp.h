@@ -89,7 +89,11 @@ typedef struct sssp_tuning {
     int32_t workgroups;    /* workgroups of the whole-GPU kernel, or of a batched launch */
     int32_t single_max_n;  /* batched plans: largest n solved by one workgroup (0 = autotune) */
     int32_t gang_columns;  /* batched plans: columns per gang member above that */
-    int32_t reserved[4];
+    int32_t group_sources; /* batched plans: sources of one shared matrix solved in lockstep by one
+                              gang, 2..16 (0 = autotune, 1 = never; see sssp_batch_plan_create) */
+    int32_t group_columns; /* batched plans: columns per member of such a gang, 512..4096, a multiple
+                              of 4 (0 = with group_sources: 1024) */
+    int32_t reserved[2];
 } sssp_tuning;
 
 /* One solve of a batch: same meaning as the arguments of sssp_dense_solve_ex. */
@@ -185,8 +189,13 @@ int32_t sssp_batch_max_n(void);
  * workgroups that share an instance's columns) unless `tuning` fixes one,
  * keeps the fastest, and captures the launch into a hipGraph.  A launch
  * replays the graph on `stream`: one persistent kernel for all instances.
- * Instances of a matrix shared by 32 or more instances are always solved by
- * one workgroup each.  When it measures splits, it also solves each other
+ * Instances of a matrix shared by 32 or more instances are solved by one
+ * workgroup each, or, when that matrix has n <= 16384 and no off-diagonal
+ * weight below 1, in groups of `group_sources` sources run in lockstep by a
+ * gang (shared-row relaxation: each round reads a row once for every source
+ * of the group whose current bucket holds it; same dist/pred as alone); the
+ * plan measures group sizes and keeps them only if the launch is faster, unless
+ * `tuning` fixes group_sources (1 = never).  When it measures splits, it also solves each other
  * distinct matrix once (from its first instance's source, into scratch
  * buffers): a matrix whose solve takes 64 or more rounds (many distinct
  * distances) is a candidate for the label-correcting method, which is kept
@@ -209,6 +218,9 @@ typedef struct sssp_plan_info {
     double build_ms;                     /* wall time of sssp_batch_plan_create */
     int32_t lc_instances;                /* instances solved with the label-correcting method */
     int32_t lc_candidates;               /* instances whose matrix qualified for it */
+    int32_t group_sources, group_columns; /* the chosen lockstep groups (0: none) */
+    int32_t group_items;                 /* groups in the launch */
+    int32_t group_candidates;            /* instances whose matrix qualified for them */
 } sssp_plan_info;
 
 /* How a batched launch splits its instances (the item order and gang shapes of

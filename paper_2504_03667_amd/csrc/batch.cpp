@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "multi.h"
 #include "sssp_internal.h"
 
 namespace sssp {
@@ -46,8 +47,10 @@ struct Source {
 struct Build {
     std::vector<BatchItem> items;  // largest first
     std::vector<BatchPart> parts;
+    std::vector<MultiSrc> groups;  // sources of the lockstep groups; an item's `group` holds its first index
     uint64_t arena_bytes = 0;
     int32_t max_parts = 1;
+    int32_t group_items = 0;
 };
 
 bool aligned(const void* p, int64_t ld, int elem) {
@@ -64,13 +67,35 @@ constexpr int32_t kSharedSources = 32;
 // times the rows of a Dijkstra solve, so it is spread over many workgroups.
 constexpr int32_t kLcColumns = 256;
 
+// Lockstep groups (multi.h): matrices up to this n; slices of 512..4096 columns.
+constexpr int32_t kGroupMaxN = 16384;
+
+// Shape of a group of up to `want` sources on an n-vertex matrix with slices of
+// `cols` columns: *S columns per member, *parts members, and the sources per
+// group (at most 4 per thread: 4 times the row partitions of a 1024-thread
+// workgroup over S columns, and at most kMultiMax).
+void group_shape(int32_t n, int32_t want, int32_t cols, int32_t* S, int32_t* parts, int32_t* K) {
+    int32_t s = std::min<int32_t>(cols, (n + 3) & ~3);
+    int32_t L = 1;
+    while (L < (s + 3) / 4 && L < 1024) L <<= 1;
+    const int32_t P = 1024 / L;
+    *S = s;
+    *parts = (n + s - 1) / s;
+    *K = std::max<int32_t>(1, std::min<int32_t>({want, kMultiMax, 4 * P}));
+}
+
 // Items in largest-first order (instances of shared matrices last); an instance
 // with n > single_max_n is split into parts of at most gang_columns columns
 // solved by a gang of workgroups.  lc (may be null): per instance, solve it
 // with the label-correcting method (never for shared matrices).
+// group_k > 1 (with group_ok marking the eligible instances): instances of a
+// shared matrix are solved group_k at a time in lockstep by gangs of group_cols
+// columns per member (kMethodGroup items, queued between the other instances
+// and the remaining shared ones).
 int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t single_max_n,
           int32_t gang_columns, int32_t max_parts, Build* out, const char* lc = nullptr,
-          std::vector<int32_t>* order_out = nullptr) {
+          std::vector<int32_t>* order_out = nullptr, int32_t group_k = 0, int32_t group_cols = 0,
+          const char* group_ok = nullptr) {
     std::vector<int32_t> order(count);
     for (int32_t i = 0; i < count; ++i) order[i] = i;
     std::map<std::pair<const void*, int64_t>, int32_t> uses;
@@ -84,9 +109,57 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
     });
     out->items.clear();
     out->parts.clear();
+    out->groups.clear();
     out->arena_bytes = 0;
     out->max_parts = 1;
+    out->group_items = 0;
+    std::vector<char> grouped(count, 0);
+    bool groups_done = false;
+    auto emit_groups = [&]() {
+        groups_done = true;
+        if (group_k < 2 || !group_ok) return;
+        // eligible shared instances by matrix, in instance order
+        std::map<std::pair<const void*, int64_t>, std::vector<int32_t>> by_matrix;
+        for (int32_t i = 0; i < count; ++i)
+            if (shared[i] && group_ok[i] && inst[i].n <= kGroupMaxN) by_matrix[{src[i].W, src[i].ld}].push_back(i);
+        for (const auto& kv : by_matrix) {
+            const std::vector<int32_t>& ids = kv.second;
+            const sssp_instance& I0 = inst[ids.front()];
+            int32_t S = 0, parts = 0, K = 0;
+            group_shape(I0.n, group_k, group_cols, &S, &parts, &K);
+            if (K < 2 || parts > max_parts) continue;
+            for (size_t a = 0; a < ids.size(); a += (size_t)K) {
+                const int32_t k = (int32_t)std::min<size_t>((size_t)K, ids.size() - a);
+                BatchItem b;
+                memset(&b, 0, sizeof b);
+                b.W = src[ids[a]].W;
+                b.ld = src[ids[a]].ld;
+                b.elem = src[ids[a]].elem;
+                b.n = I0.n;
+                b.src = -1;
+                b.vec = aligned(b.W, b.ld, b.elem) ? 1 : 0;
+                b.method = kMethodGroup;
+                b.K = k;
+                b.S = S;
+                b.parts = parts;
+                b.group = reinterpret_cast<const void*>((uintptr_t)out->groups.size());
+                for (int32_t j = 0; j < k; ++j) {
+                    const sssp_instance& I = inst[ids[a + j]];
+                    out->groups.push_back(MultiSrc{I.src, 0, I.dist, I.pred});
+                    grouped[ids[a + j]] = 1;
+                }
+                b.scratch_off = out->arena_bytes;
+                out->arena_bytes += multi_scratch_bytes(k, parts, S);
+                out->max_parts = std::max(out->max_parts, parts);
+                for (int32_t j = 0; j < parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
+                out->items.push_back(b);
+                ++out->group_items;
+            }
+        }
+    };
     for (int32_t k = 0; k < count; ++k) {
+        if (!groups_done && shared[order[k]]) emit_groups();
+        if (grouped[order[k]]) continue;
         const sssp_instance& I = inst[order[k]];
         BatchItem b;
         memset(&b, 0, sizeof b);
@@ -120,6 +193,7 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
         for (int32_t j = 0; j < b.parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
         out->items.push_back(b);
     }
+    if (!groups_done) emit_groups();
     if (order_out) *order_out = order;
     return SSSP_OK;
 }
@@ -200,7 +274,9 @@ struct sssp_batch_plan {
     std::vector<Source> src;
     std::vector<CompactCopy> copies;
     std::vector<char> lc;  // per instance: label-correcting (empty: none)
+    std::vector<char> group_ok;  // per instance: its matrix may be solved in lockstep groups (empty: none)
     BatchItem* d_items = nullptr;
+    MultiSrc* d_groups = nullptr;
     BatchPart* d_parts = nullptr;
     int32_t nparts = 0;
     Bar* d_bars = nullptr;
@@ -217,22 +293,35 @@ struct sssp_batch_plan {
         (void)hipFree(d_parts);
         (void)hipFree(d_bars);
         (void)hipFree(d_arena);
+        (void)hipFree(d_groups);
         d_items = nullptr;
         d_parts = nullptr;
         d_bars = nullptr;
         d_arena = nullptr;
+        d_groups = nullptr;
     }
 
-    // Upload one configuration's items, parts and scratch.
-    int upload(int32_t single_max_n, int32_t gang_columns) {
+    // Upload one configuration's items, parts and scratch (group_k < 2: no lockstep groups).
+    int upload(int32_t single_max_n, int32_t gang_columns, int32_t group_k = 0, int32_t group_cols = 0) {
         Build b;
         int rc = ::build(inst.data(), src.data(), (int32_t)inst.size(), single_max_n, gang_columns,
-                         std::max(2, nwg / 2), &b, lc.empty() ? nullptr : lc.data());
+                         std::max(2, nwg / 2), &b, lc.empty() ? nullptr : lc.data(), nullptr, group_k, group_cols,
+                         group_ok.empty() ? nullptr : group_ok.data());
         if (rc) return rc;
         lc_items = 0;
         for (const BatchItem& it : b.items) lc_items += it.method == kMethodLabelCorrecting;
+        group_items = b.group_items;
         free_device();
-        hipError_t e = hipMalloc(&d_items, sizeof(BatchItem) * b.items.size());
+        hipError_t e = hipSuccess;
+        if (!b.groups.empty()) {
+            e = hipMalloc(&d_groups, sizeof(MultiSrc) * b.groups.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(d_groups, b.groups.data(), sizeof(MultiSrc) * b.groups.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return err(SSSP_ENOMEM, "group sources: %s", hipGetErrorString(e));
+            for (BatchItem& it : b.items)
+                if (it.method == kMethodGroup) it.group = d_groups + (uintptr_t)it.group;
+        }
+        e = hipMalloc(&d_items, sizeof(BatchItem) * b.items.size());
         if (e == hipSuccess) e = hipMalloc(&d_parts, sizeof(BatchPart) * b.parts.size());
         if (e == hipSuccess) e = hipMalloc(&d_bars, sizeof(Bar) * b.items.size());
         if (e == hipSuccess && b.arena_bytes) e = hipMalloc(&d_arena, b.arena_bytes);
@@ -255,6 +344,7 @@ struct sssp_batch_plan {
     }
 
     int32_t lc_items = 0;
+    int32_t group_items = 0;
 
     // Median-free timing of the uploaded configuration: best of 2 launches after a
     // warm-up (ms), or a negative value on a launch error (e set).
@@ -466,6 +556,29 @@ int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t fl
         const CompactCopy& c = p->copies[it->second];
         if (c.elem < 4) p->src[i] = Source{c.data, c.ld, c.elem};
     }
+    // matrices whose shared instances may run in lockstep groups: n <= kGroupMaxN and
+    // every off-diagonal weight >= 1 (fused rounds then never fall back)
+    const int32_t want_group = tuning ? tuning->group_sources : 0;
+    if (!(flags & (SSSP_FLAG_LITERAL | SSSP_FLAG_LABEL_CORRECTING))) {
+        std::map<std::pair<const int32_t*, int64_t>, std::vector<int32_t>> by_matrix;
+        for (int32_t i = 0; i < count; ++i) by_matrix[{inst[i].W, inst[i].ld}].push_back(i);
+        p->group_ok.assign(count, 0);
+        for (const auto& kv : by_matrix) {
+            const sssp_instance& I = inst[kv.second.front()];
+            if ((int32_t)kv.second.size() < kSharedSources || I.n > kGroupMaxN || I.n > max_batch_single_n()) continue;
+            int32_t wmin = 0, wmax = 0, woff = 0;
+            auto cit = seen.find(kv.first);
+            if (cit != seen.end()) {
+                woff = p->copies[cit->second].woff;
+            } else if ((rc = matrix_range(I.W, I.ld, I.n, s, &wmin, &wmax, &woff))) {
+                return fail(rc);
+            }
+            if (woff < 1) continue;
+            for (int32_t i : kv.second) p->group_ok[i] = 1;
+            p->info.group_candidates += (int32_t)kv.second.size();
+        }
+        if (p->info.group_candidates == 0) p->group_ok.clear();
+    }
     hipError_t e = hipMalloc(&p->d_ctl, ctl_size());
     if (e == hipSuccess) e = hipMemset(p->d_ctl, 0, ctl_size());
     if (e != hipSuccess) return fail(err(SSSP_ENOMEM, "plan control block: %s", hipGetErrorString(e)));
@@ -531,8 +644,60 @@ int sssp_batch_plan_create(const sssp_instance* inst, int32_t count, uint32_t fl
         p->lc.assign(count, 1);
     }
     if (flags & SSSP_FLAG_LABEL_CORRECTING) p->lc.assign(count, 1);
-    rc = p->upload(best.single_max_n, best.gang_columns);
+    // lockstep groups of the shared matrices' instances: fixed by the tuning, or
+    // measured (group size, columns per member) and kept only if the launch is faster
+    struct GroupCand {
+        int32_t k, cols;
+    };
+    GroupCand gbest{0, 0};
+    if (!p->group_ok.empty() && want_group != 1) {
+        if (want_group >= 2) {
+            gbest = GroupCand{std::min<int32_t>(want_group, kMultiMax),
+                              tuning->group_columns > 0 ? tuning->group_columns : 1024};
+        } else {
+            (void)hipEventCreate(&ev0);
+            (void)hipEventCreate(&ev1);
+            auto measure = [&](const GroupCand& g, float* ms) -> int {
+                int r = p->upload(best.single_max_n, best.gang_columns, g.k, g.cols);
+                if (r) return r;
+                *ms = p->time_launches(s, ev0, ev1, e);
+                if (e != hipSuccess) return hip_err(e, "autotuning launch");
+                p->info.candidates += 1;
+                return SSSP_OK;
+            };
+            float ms = 0;
+            if (best_ms >= 1e29) {  // the split was fixed: time it without groups first
+                if ((rc = measure(GroupCand{0, 0}, &ms))) {
+                    (void)hipEventDestroy(ev0);
+                    (void)hipEventDestroy(ev1);
+                    return fail(rc);
+                }
+                best_ms = ms;
+            }
+            // shapes with at most two sources per thread (4 per 1024-column slice, 2 per
+            // 2048, 1..2 per 4096, 8 per 512 / 1024): the wider ones spill registers
+            for (const GroupCand& g : {GroupCand{8, 1024}, GroupCand{4, 2048}, GroupCand{2, 4096}, GroupCand{16, 512}}) {
+                if ((rc = measure(g, &ms))) {
+                    (void)hipEventDestroy(ev0);
+                    (void)hipEventDestroy(ev1);
+                    return fail(rc);
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    gbest = g;
+                }
+            }
+            (void)hipEventDestroy(ev0);
+            (void)hipEventDestroy(ev1);
+        }
+    }
+    if (gbest.cols % 4 || (gbest.k && (gbest.cols < 512 || gbest.cols > 4096)))
+        return fail(err(SSSP_EINVAL, "group_columns %d: a multiple of 4 in [512, 4096]", gbest.cols));
+    rc = p->upload(best.single_max_n, best.gang_columns, gbest.k, gbest.cols);
     if (rc) return fail(rc);
+    p->info.group_sources = p->group_items ? gbest.k : 0;
+    p->info.group_columns = p->group_items ? gbest.cols : 0;
+    p->info.group_items = p->group_items;
     p->info.lc_instances = p->lc_items;
     p->info.threads = 1024;
     p->info.workgroups = p->nwg;

@@ -27,6 +27,7 @@
 
 #include "engine.h"
 #include "lc.h"
+#include "multi.h"
 #include "solve.h"
 #include "sssp_internal.h"
 
@@ -137,6 +138,35 @@ __device__ __attribute__((noinline)) SolveStats lc_variant(BatchItem I, int part
     return st;
 }
 
+// A group of I.K sources of one matrix in lockstep (rank `part` of a gang of
+// I.parts, possibly one).
+template <int T, int KP, typename E>
+__device__ __attribute__((noinline)) SolveStats group_variant(BatchItem I, int part, long long timeout, Bar* bw,
+                                                              char* arena, uint32_t epoch) {
+    SolveStats st = {0, 0, 0, 0, 0};
+    const int rw = multi_rec_words(I.K);
+    uint64_t* recs = reinterpret_cast<uint64_t*>(arena + I.scratch_off);
+    uint32_t* lists = reinterpret_cast<uint32_t*>(recs + 2 * (size_t)I.parts * rw);
+    solve_multi<T, KP, E>(static_cast<const E*>(I.W), I.ld, I.n, static_cast<const MultiSrc*>(I.group), I.K,
+                          I.vec != 0, I.S, part, I.parts, timeout, recs, lists, g_sh<T>, g_mh<T>, st, epoch);
+    if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
+    return st;
+}
+
+// Sources per thread of a group: the K sources spread over the P = T / L row
+// partitions of a slice of I.S columns (the host keeps K <= 4P).
+template <int T, typename E>
+__device__ __forceinline__ SolveStats group_by_shape(const BatchItem& I, int part, long long timeout, Bar* bw,
+                                                     char* arena, uint32_t epoch) {
+    int L = 1;
+    while (L < (I.S + 3) / 4 && L < T) L <<= 1;
+    const int P = T / L;
+    const int kp = (I.K + P - 1) / P;
+    if (kp <= 1) return group_variant<T, 1, E>(I, part, timeout, bw, arena, epoch);
+    if (kp <= 2) return group_variant<T, 2, E>(I, part, timeout, bw, arena, epoch);
+    return group_variant<T, 4, E>(I, part, timeout, bw, arena, epoch);
+}
+
 template <int T, typename E>
 __device__ __forceinline__ SolveStats lc_by_size(const BatchItem& I, int part, long long timeout, Bar* bw,
                                                  char* arena, uint32_t epoch) {
@@ -167,6 +197,11 @@ template <int T>
 // epoch: unique to this use of the item's exchange records (see gang_exchange).
 __device__ __forceinline__ SolveStats solve_item(const BatchItem& I, int part, bool literal, long long timeout,
                                                  Bar* bw, char* arena, uint32_t epoch) {
+    if (I.method == kMethodGroup) {
+        if (I.elem == 1) return group_by_shape<T, uint8_t>(I, part, timeout, bw, arena, epoch);
+        if (I.elem == 2) return group_by_shape<T, uint16_t>(I, part, timeout, bw, arena, epoch);
+        return group_by_shape<T, int32_t>(I, part, timeout, bw, arena, epoch);
+    }
     if (I.method == kMethodLabelCorrecting && !literal) {
         if (I.elem == 1) return lc_by_size<T, uint8_t>(I, part, timeout, bw, arena, epoch);
         if (I.elem == 2) return lc_by_size<T, uint16_t>(I, part, timeout, bw, arena, epoch);

@@ -58,15 +58,19 @@ struct BatchItem {
     int32_t vec;         // rows aligned for whole-group loads
     int32_t parts;       // workgroups that solve it (1: one workgroup alone; > 1: a gang)
     int32_t S;           // columns per gang member
-    int32_t method;      // kMethodDijkstra or kMethodLabelCorrecting
-    int32_t pad;
+    int32_t method;      // kMethodDijkstra, kMethodLabelCorrecting or kMethodGroup
+    int32_t K;           // kMethodGroup: sources of the group (src, dist, pred above unused)
     unsigned long long scratch_off;  // byte offset of a gang's records and lists in the arena
+    const void* group;   // kMethodGroup: device array of K MultiSrc (multi.h)
 };
 
 // BatchItem::method.  Label-correcting items always run as a gang (possibly of
 // one) with exchange records and 64-bit lists in the arena.
 constexpr int32_t kMethodDijkstra = 0;
 constexpr int32_t kMethodLabelCorrecting = 1;
+// Several sources of one matrix solved in lockstep by a gang (multi.h); only for
+// matrices whose off-diagonal weights are all >= 1.
+constexpr int32_t kMethodGroup = 2;
 
 // Arena bytes of an item's exchange records and lists (0 for a Dijkstra item
 // solved by one workgroup).

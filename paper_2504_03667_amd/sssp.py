@@ -46,7 +46,8 @@ class SsspError(RuntimeError):
 class sssp_tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("single_max_n", ctypes.c_int32), ("gang_columns", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("group_sources", ctypes.c_int32), ("group_columns", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class sssp_plan_info(ctypes.Structure):
@@ -56,7 +57,9 @@ class sssp_plan_info(ctypes.Structure):
                 ("compact_graphs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("compact_bytes", ctypes.c_int64), ("tuned_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("lc_instances", ctypes.c_int32),
-                ("lc_candidates", ctypes.c_int32)]
+                ("lc_candidates", ctypes.c_int32), ("group_sources", ctypes.c_int32),
+                ("group_columns", ctypes.c_int32), ("group_items", ctypes.c_int32),
+                ("group_candidates", ctypes.c_int32)]
 
 
 class sssp_instance(ctypes.Structure):
@@ -201,12 +204,13 @@ def _ptr(t, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _tuning(threads=0, workgroups=0, single_max_n=0, gang_columns=0):
-    if not (threads or workgroups or single_max_n or gang_columns):
+def _tuning(threads=0, workgroups=0, single_max_n=0, gang_columns=0, group_sources=0, group_columns=0):
+    if not (threads or workgroups or single_max_n or gang_columns or group_sources or group_columns):
         return None
     t = sssp_tuning()
     t.threads, t.workgroups = threads, workgroups
     t.single_max_n, t.gang_columns = single_max_n, gang_columns
+    t.group_sources, t.group_columns = group_sources, group_columns
     return ctypes.byref(t)
 
 
@@ -343,11 +347,11 @@ def sssp_dense_validate(W, ld, n, stream=None):
 
 
 def sssp_batch_plan_create(items, flags=0, threads=0, workgroups=0, single_max_n=0, gang_columns=0,
-                           stream=None):
+                           group_sources=0, group_columns=0, stream=None):
     arr, count = make_instances(items)
     h = ctypes.c_void_p()
     _check(lib().sssp_batch_plan_create(arr, count, flags, _tuning(threads, workgroups, single_max_n,
-                                                                    gang_columns),
+                                                                    gang_columns, group_sources, group_columns),
                                         _stream(stream), ctypes.byref(h)))
     return h
 

@@ -12,6 +12,7 @@
 
 #include "engine.h"
 #include "lc.h"
+#include "multi.h"
 #include "sssp_internal.h"
 
 using namespace sssp;
@@ -65,6 +66,25 @@ int main() {
                       S = 4 * (1 + (int32_t)(rng() % 4096));
         const unsigned long long bytes = item_scratch_bytes(method, parts, S, sizeof(Pub));
         CHECK(bytes % 256 == 0);
+        if (failures > 10) break;
+    }
+    // lockstep-group records: whole 32-byte multiples, every word but the stamp
+    // below 2^63 (keys at most kRecNone, counts and lengths below 2^31), list
+    // entries (column << 16 | mask) with the column below 4096, and arena regions
+    // of 256-byte multiples
+    CHECK(kRecNone >> 63 == 0u);
+    for (int K = 1; K <= kMultiMax; ++K) {
+        CHECK(multi_rec_words(K) % 4 == 0);
+        CHECK(multi_rec_words(K) >= 2 + K + (K + 1) / 2);
+        for (int parts = 1; parts <= 32; ++parts)
+            for (int S = 512; S <= 4096; S += 4) CHECK(multi_scratch_bytes(K, parts, S) % 256 == 0);
+    }
+    for (int i = 0; i < 100000; ++i) {
+        const uint32_t col = (uint32_t)(rng() % 4096), mask = (uint32_t)(rng() & 0xffffu);
+        const uint32_t e1 = (col << 16) | mask, e2 = ((uint32_t)(rng() % 4096) << 16) | (uint32_t)(rng() & 0xffffu);
+        CHECK((((uint64_t)e1 << 32) | e2) >> 63 == 0u);
+        const uint64_t key = make_key((uint32_t)(rng() % kInf), (uint32_t)(rng() & 0x7fffffffu));
+        CHECK(key >> 63 == 0u && key < kRecNone);
         if (failures > 10) break;
     }
     if (failures) return 1;
