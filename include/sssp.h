@@ -142,7 +142,7 @@ int sssp_dense_solve_ex(const int32_t* W, int64_t ld, int32_t n, int32_t src, in
  * must start at zero with a fill kernel, so no call depends on the previous
  * one's leftovers.  Asynchronous, like sssp_dense_solve.
  */
-#define SSSP_NOALLOC_SCRATCH_BYTES (4u << 20)
+#define SSSP_NOALLOC_SCRATCH_BYTES (8u << 20)
 #define SSSP_NOALLOC_MAX_N 262144
 int sssp_dense_solve_noalloc(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist,
                              int32_t* pred, uint32_t flags, int32_t* status, void* stream);

@@ -31,6 +31,17 @@ SO_STRESS = os.path.join(HERE, "libsssp_stress.so")
 VARIANTS = ((SO, BUILD, []), (SO_STRESS, BUILD + "_stress", ["-DSSSP_STRESS_DELAYS=1"]))
 
 
+# GPU test programs built from the library's headers (run by the gpu-marked tests).
+TEST_NATIVE = os.path.join(ROOT, "tests", "native")
+TEST_PROGRAMS = [(os.path.join(TEST_NATIVE, "wave_ops.hip"), os.path.join(TEST_NATIVE, "_build", "wave_ops"))]
+
+
+def build_test_program(src, exe):
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    _run([HIPCC] + FLAGS + ["-x", "hip", src, "-o", exe + ".tmp"])
+    os.replace(exe + ".tmp", exe)
+
+
 def build(verbose=False):
     jobs = []
     for so, folder, extra in VARIANTS:
@@ -46,8 +57,11 @@ def build(verbose=False):
             sys.stderr.write(err)
         return obj
 
-    with ThreadPoolExecutor(min(len(jobs), os.cpu_count() or 8)) as ex:
+    with ThreadPoolExecutor(min(len(jobs) + len(TEST_PROGRAMS), os.cpu_count() or 8)) as ex:
+        tests = [ex.submit(build_test_program, src, exe) for src, exe in TEST_PROGRAMS]
         objs = list(ex.map(compile_one, jobs))
+        for t in tests:
+            t.result()
     for i, (so, _, _) in enumerate(VARIANTS):
         tmp = so + ".tmp"
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] +

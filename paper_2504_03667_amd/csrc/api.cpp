@@ -44,12 +44,8 @@ struct Scratch {
     int device = -1;
     hipStream_t stream = nullptr;
     Ctl* ctl = nullptr;
-    Pub* pubs = nullptr;
-    size_t pubs_cap = 0;
-    int32_t* lists = nullptr;
-    size_t lists_cap = 0;
-    uint64_t* lists64 = nullptr;  // label-correcting frontier lists
-    size_t lists64_cap = 0;
+    char* words = nullptr;  // exchange records and lists of the whole-GPU solves (gang_words_bytes)
+    size_t words_cap = 0;
     bool launched = false;
 };
 
@@ -114,7 +110,7 @@ int ensure(Scratch* sc, X*& p, size_t& cap, size_t need, const char* what) {
     hipError_t e = hipMalloc(&p, n * sizeof(X));
     if (e != hipSuccess) return fail(SSSP_ENOMEM, "hipMalloc(%s, %zu bytes): %s", what, n * sizeof(X),
                                      hipGetErrorString(e));
-    // exchange records must start without stamps (see gang_exchange)
+    // stamped records must start without stamps (see gang_exchange)
     e = hipMemset(p, 0, n * sizeof(X));
     if (e != hipSuccess) return hip_fail(e, "hipMemset(scratch)");
     cap = n;
@@ -164,8 +160,7 @@ int check_solve_args(const int32_t* W, int64_t ld, int32_t n, int32_t src, const
 
 // Device bytes held by one scratch block.
 size_t block_bytes(const Scratch& s) {
-    return (s.ctl ? ctl_size() : 0) + s.pubs_cap * sizeof(Pub) + s.lists_cap * sizeof(int32_t) +
-           s.lists64_cap * sizeof(uint64_t);
+    return (s.ctl ? ctl_size() : 0) + s.words_cap;
 }
 
 // Waits for the block's stream, then frees its device memory.  Caller holds g_mu.
@@ -175,14 +170,10 @@ void free_block(Scratch& s) {
     if (cur != s.device) (void)hipSetDevice(s.device);
     (void)hipStreamSynchronize(s.stream);
     (void)hipFree(s.ctl);
-    (void)hipFree(s.pubs);
-    (void)hipFree(s.lists);
-    (void)hipFree(s.lists64);
+    (void)hipFree(s.words);
     s.ctl = nullptr;
-    s.pubs = nullptr;
-    s.lists = nullptr;
-    s.lists64 = nullptr;
-    s.pubs_cap = s.lists_cap = s.lists64_cap = 0;
+    s.words = nullptr;
+    s.words_cap = 0;
     if (cur >= 0 && cur != s.device) (void)hipSetDevice(cur);
 }
 
@@ -272,17 +263,13 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         rc = grid_shape(n, tuning && tuning->workgroups ? tuning->workgroups : 0, lc, lc && (flags & SSSP_FLAG_SINGLE),
                         di.cus, &nwg, &S);
         if (rc) return rc;
-        rc = ensure(sc, sc->pubs, sc->pubs_cap, 2 * (size_t)nwg, "exchange records");
+        rc = ensure(sc, sc->words, sc->words_cap, gang_words_bytes(nwg, S), "exchange records and lists");
         if (rc) return rc;
         if (lc) {
-            rc = ensure(sc, sc->lists64, sc->lists64_cap, 2 * (size_t)nwg * S, "frontier lists");
-            if (rc) return rc;
-            e = launch_lc(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists64, plain_grid_launch(), stream);
+            e = launch_lc(a, nwg, S, barrier_timeout_ticks(di), sc->words, plain_grid_launch(), stream);
             if (e != hipSuccess) return hip_fail(e, "cooperative launch(label-correcting solve)");
         } else {
-            rc = ensure(sc, sc->lists, sc->lists_cap, 2 * (size_t)nwg * S, "bucket lists");
-            if (rc) return rc;
-            e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->pubs, sc->lists, plain_grid_launch(), stream);
+            e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->words, plain_grid_launch(), stream);
             if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
         }
     }

@@ -187,7 +187,7 @@ int build(const sssp_instance* inst, const Source* src, int32_t count, int32_t s
             b.S = (int32_t)s;
             b.parts = (int32_t)(((int64_t)I.n + s - 1) / s);
             b.scratch_off = out->arena_bytes;
-            out->arena_bytes += item_scratch_bytes(b.method, b.parts, b.S, pub_size());
+            out->arena_bytes += item_scratch_bytes(b.method, b.parts, b.S);
             out->max_parts = std::max(out->max_parts, b.parts);
         }
         for (int32_t j = 0; j < b.parts; ++j) out->parts.push_back(BatchPart{(int32_t)out->items.size(), j});
@@ -435,7 +435,7 @@ int sssp_batch_layout(const sssp_instance* inst, int32_t count, uint32_t flags, 
     if (rc) return rc;
     for (int32_t k = 0; k < count; ++k) {
         const BatchItem& it = b.items[k];
-        const unsigned long long bytes = item_scratch_bytes(it.method, it.parts, it.S, pub_size());
+        const unsigned long long bytes = item_scratch_bytes(it.method, it.parts, it.S);
         out[k] = sssp_layout_entry{order[k], it.parts, it.S, it.method,
                                    bytes ? (int64_t)it.scratch_off : -1, (int64_t)bytes};
     }

@@ -97,6 +97,35 @@ struct alignas(32) Pub {
     uint32_t flags;  // bit 0: a zero-weight edge from the bucket to an unvisited vertex was seen
     uint64_t pad;
 };
+static_assert(sizeof(Pub) == 32, "stamped records are 32 bytes");
+
+// Tagged exchange words.  After the first exchange of a gang's solve, every
+// word a member publishes carries the number b of its exchange in the high 32
+// bits (the word's tag) and a 32-bit value in the low ones, so a reader takes
+// each word as soon as it shows the tag it waits for: a member neither waits
+// for its own stores to complete nor orders them behind a stamp.  Each member
+// clears its tagged words (tag 0) before the solve's first exchange, which
+// uses stamps and so completes every member's earlier stores before anyone
+// passes it; from then on a tagged word holds 0, a tag of an earlier exchange
+// of the same solve (b - 2, b - 4, ... in the same slot) or the awaited one,
+// and the tag of exchange b is b >= 1, below 2^32 because a solve of n < 2^31
+// vertices has at most 2n + 1 exchanges.
+__host__ __device__ constexpr uint64_t tag_word(uint32_t tag, uint32_t value) {
+    return ((uint64_t)tag << 32) | value;
+}
+__host__ __device__ constexpr uint32_t word_tag(uint64_t w) { return (uint32_t)(w >> 32); }
+
+// A gang's tagged records of the Dijkstra rounds, as a structure of arrays:
+// for each slot (exchange parity) and field, nwg consecutive words (member g at
+// index g), so that a wave reading the words of 64 consecutive members touches
+// four cache lines instead of one per member.  Fields: the dist of the
+// member's key (0xffffffff: no key), the key's vertex, and (count << 1) | the
+// zero-weight hazard flag; each word tagged.  The fourth field is unused
+// (32 bytes per member and slot).
+enum { kRecDist = 0, kRecVert = 1, kRecCnt = 2, kRecFields = 4 };
+__host__ __device__ inline uint64_t* rec_word(uint64_t* recs, int nwg, uint32_t slot, int field, int g) {
+    return recs + ((size_t)slot * kRecFields + (size_t)field) * (size_t)nwg + (size_t)g;
+}
 
 template <typename X>
 __device__ __forceinline__ X ld_agent(const X* p) {
@@ -108,9 +137,11 @@ __device__ __forceinline__ void st_agent(X* p, X v) {
 }
 
 // Barrier stress (the separately built libsssp_stress.so only): before it
-// arrives at an exchange, a workgroup pauses for a pseudo-random 0 to ~25 us
-// chosen by (workgroup, key), so that tests see many arrival orders and late
-// members.  Compiled out of the product library.
+// arrives at an exchange (its stamp or barrier arrival; in a tagged exchange,
+// its list entries and, separately, its record), a workgroup pauses for a
+// pseudo-random 0 to ~25 us chosen by (workgroup, key), so that tests see many
+// arrival orders, late members and entries that arrive after their record.
+// Compiled out of the product library.
 __device__ __forceinline__ void stress_delay(uint32_t key) {
 #ifdef SSSP_STRESS_DELAYS
     uint32_t h = (blockIdx.x + 1u) * 0x9E3779B9u ^ (key * 0x85EBCA6Bu);
@@ -142,30 +173,54 @@ __device__ __forceinline__ uint32_t xor_lane32(uint32_t x, int lane, int o) {
     return (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ o) << 2, (int)x);
 }
 
-__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
-    const int lane = wave_lane();
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t y = ((uint64_t)xor_lane32((uint32_t)(x >> 32), lane, o) << 32) | xor_lane32((uint32_t)x, lane, o);
-        x = umin64(x, y);
-    }
-    return x;
+// Wave-wide reductions and scans, which every caller runs with all 64 lanes
+// active.  Inside each row of 16 lanes they use DPP row shifts (a VALU operand
+// read from the lane k below, no LDS round trip: ds_bpermute chains made the
+// per-round reductions cost about 1 us each); the four row results are then
+// combined from lanes 15, 31, 47 and 63 with v_readlane (scalar registers).
+// row_shr:k; a lane with no source lane in its row gets `old`.
+template <int K>
+__device__ __forceinline__ uint32_t row_shr(uint32_t old, uint32_t x) {
+    static_assert(K >= 1 && K <= 15, "row_shr:1..15");
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, 0x110 + K, 0xf, 0xf, false);
 }
+template <int K>
+__device__ __forceinline__ uint64_t row_shr64(uint64_t x) {  // a lane with no source keeps x
+    return ((uint64_t)row_shr<K>((uint32_t)(x >> 32), (uint32_t)(x >> 32)) << 32) |
+           row_shr<K>((uint32_t)x, (uint32_t)x);
+}
+__device__ __forceinline__ uint32_t lane_value(uint32_t x, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ uint64_t lane_value64(uint64_t x, int l) {
+    return ((uint64_t)lane_value((uint32_t)(x >> 32), l) << 32) | lane_value((uint32_t)x, l);
+}
+
+// minimum over the wave, in every lane
+__device__ __forceinline__ uint64_t wave_min64(uint64_t x) {
+    x = umin64(x, row_shr64<1>(x));
+    x = umin64(x, row_shr64<2>(x));
+    x = umin64(x, row_shr64<4>(x));
+    x = umin64(x, row_shr64<8>(x));  // lane 15 of each row: the row's minimum
+    return umin64(umin64(lane_value64(x, 15), lane_value64(x, 31)), umin64(lane_value64(x, 47), lane_value64(x, 63)));
+}
+// OR over the wave, in every lane
 __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
-    const int lane = wave_lane();
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= xor_lane32(x, lane, o);
-    return x;
+    x |= row_shr<1>(0u, x);
+    x |= row_shr<2>(0u, x);
+    x |= row_shr<4>(0u, x);
+    x |= row_shr<8>(0u, x);
+    return lane_value(x, 15) | lane_value(x, 31) | lane_value(x, 47) | lane_value(x, 63);
 }
 // inclusive prefix sum over the wave
 __device__ __forceinline__ uint32_t wave_scan32(uint32_t x) {
-    const int lane = wave_lane();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute((lane - o) << 2, (int)x);
-        if (lane >= o) x += y;
-    }
-    return x;
+    x += row_shr<1>(0u, x);
+    x += row_shr<2>(0u, x);
+    x += row_shr<4>(0u, x);
+    x += row_shr<8>(0u, x);  // prefix within the row
+    const uint32_t r0 = lane_value(x, 15), r1 = lane_value(x, 31), r2 = lane_value(x, 47);
+    const int row = wave_lane() >> 4;
+    return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
 }
 
 // LDS scratch for block-wide reductions (one slot per wave).

@@ -58,13 +58,12 @@ template <int T, int G, int U>
 __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
                                             int32_t src, int32_t* __restrict__ dist,
                                             int32_t* __restrict__ pred, uint32_t flags, int32_t S,
-                                            long long timeout, Ctl* __restrict__ ctl,
-                                            Pub* __restrict__ pubs, int32_t* __restrict__ lists) {
+                                            long long timeout, Ctl* __restrict__ ctl, char* __restrict__ words) {
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
     const uint32_t epoch = ld_agent(&ctl->epoch);
     solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
-                        blockIdx.x, gridDim.x, timeout, &ctl->b, pubs, lists, sh, st, ctl, epoch);
+                        blockIdx.x, gridDim.x, timeout, gang_words(words, gridDim.x), sh, st, ctl, epoch);
     finish_launch(ctl, st, blockIdx.x == 0);
 }
 
@@ -98,11 +97,9 @@ template <int T, int G, typename E>
 __device__ __attribute__((noinline)) SolveStats gang_variant(BatchItem I, int part, bool literal, long long timeout,
                                                              Bar* bw, char* arena, uint32_t epoch) {
     SolveStats st = {0, 0, 0, 0, 0};
-    Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
-    int32_t* lists = reinterpret_cast<int32_t*>(pubs + 2 * I.parts);
     solve_gang<T, G, rows_in_flight<E>(), E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
-                                            I.vec != 0, literal, I.S,
-                           part, I.parts, timeout, bw, pubs, lists, g_sh<T>, st, nullptr, epoch);
+                                            I.vec != 0, literal, I.S, part, I.parts, timeout,
+                                            gang_words(arena + I.scratch_off, I.parts), g_sh<T>, st, nullptr, epoch);
     if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
     return st;
 }
@@ -114,18 +111,16 @@ template <int T, int G, typename E>
 __device__ __attribute__((noinline)) SolveStats lc_variant(BatchItem I, int part, long long timeout, Bar* bw,
                                                            char* arena, uint32_t epoch) {
     SolveStats st = {0, 0, 0, 0, 0};
-    Pub* pubs = reinterpret_cast<Pub*>(arena + I.scratch_off);
-    uint64_t* lists = reinterpret_cast<uint64_t*>(pubs + 2 * I.parts);
+    const GangWords gw = gang_words(arena + I.scratch_off, I.parts);
     uint32_t b = 0;
     const int r = solve_lc<T, G, 8, E, false>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
-                                              I.vec != 0, I.S, part, I.parts, timeout, bw, pubs, lists, g_sh<T>,
+                                              I.vec != 0, I.S, part, I.parts, timeout, bw, gw.pubs, gw.lists, g_sh<T>,
                                               g_lc<T>, st, b, epoch, nullptr);
     if (r == kLcFallback) {
         ++st.fallbacks;
         st.status |= kStatusZeroFallback;
         solve_gang<T, G, 8, E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred, I.vec != 0, false,
-                               I.S, part, I.parts, timeout, bw, pubs, reinterpret_cast<int32_t*>(lists), g_sh<T>,
-                               st, nullptr, epoch, b);
+                               I.S, part, I.parts, timeout, gw, g_sh<T>, st, nullptr, epoch, b);
     } else {
         if (r == kLcTimeout) st.status |= kStatusTimeout;
         st.barriers += b;
@@ -421,8 +416,8 @@ hipError_t launch_single(const SolveArgs& a, int threads, hipStream_t s) {
 int max_single_n() { return 4 * 4 * 1024; }
 
 template <int T, int G, int U>
-static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs,
-                                int32_t* lists, bool plain, hipStream_t s) {
+static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+                                hipStream_t s) {
     const int32_t* W = a.W;
     int64_t ld = a.ld;
     int32_t n = a.n, src = a.src;
@@ -432,20 +427,20 @@ static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long ti
     Ctl* ctl = a.ctl;
     if (plain) {
         hipLaunchKernelGGL((k_grid<T, G, U>), dim3(nwg), dim3(T), 0, s, W, ld, n, src, dist, pred, flags, S,
-                           timeout, ctl, pubs, lists);
+                           timeout, ctl, words);
         return hipGetLastError();
     }
-    void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &pubs, &lists};
+    void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &words};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid<T, G, U>), dim3(nwg),
                                       dim3(T), args, 0, s);
 }
 
-hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, int32_t* lists,
-                       bool plain, hipStream_t s) {
+hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+                       hipStream_t s) {
     const int groups = (S + 3) / 4;
-    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
-    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
-    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
+    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, words, plain, s);
     return hipErrorInvalidValue;
 }
 
@@ -516,6 +511,5 @@ int max_serve_slice() { return 4 * 4 * 1024; }
 
 namespace sssp {
 size_t ctl_size() { return sizeof(Ctl); }
-size_t pub_size() { return sizeof(Pub); }
 size_t bar_size() { return sizeof(Bar); }
 }  // namespace sssp

@@ -14,14 +14,15 @@ template <int T, int G, int U>
 __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                                           int32_t* __restrict__ dist, int32_t* __restrict__ pred, uint32_t flags,
                                           int32_t S, long long timeout, Ctl* __restrict__ ctl,
-                                          Pub* __restrict__ pubs, uint64_t* __restrict__ lists) {
+                                          char* __restrict__ words) {
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
     uint32_t b = 0;
     const bool vec = (flags & kFlagVec) != 0;
     const uint32_t epoch = ld_agent(&ctl->epoch);
+    const GangWords gw = gang_words(words, gridDim.x);
     const int r = solve_lc<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, vec, S, blockIdx.x, gridDim.x, timeout,
-                                                   &ctl->b, pubs, lists, sh, g_lc<T>, st, b, epoch, ctl);
+                                                   &ctl->b, gw.pubs, gw.lists, sh, g_lc<T>, st, b, epoch, ctl);
     if (r == kLcTimeout) {
         st.status |= kStatusTimeout;
         st.barriers += b;
@@ -31,7 +32,7 @@ __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t
         ++st.fallbacks;
         st.status |= kStatusZeroFallback;
         solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, vec, false, S, blockIdx.x, gridDim.x, timeout,
-                                           &ctl->b, pubs, reinterpret_cast<int32_t*>(lists), sh, st, ctl, epoch, b);
+                                           gw, sh, st, ctl, epoch, b);
     } else {
         st.barriers += b;
     }
@@ -48,8 +49,8 @@ __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t
 }
 
 template <int T, int G, int U>
-static hipError_t launch_lc_t(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, uint64_t* lists,
-                              bool plain, hipStream_t s) {
+static hipError_t launch_lc_t(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+                              hipStream_t s) {
     const int32_t* W = a.W;
     int64_t ld = a.ld;
     int32_t n = a.n, src = a.src;
@@ -59,19 +60,19 @@ static hipError_t launch_lc_t(const SolveArgs& a, int nwg, int S, long long time
     Ctl* ctl = a.ctl;
     if (plain) {
         hipLaunchKernelGGL((k_lc<T, G, U>), dim3(nwg), dim3(T), 0, s, W, ld, n, src, dist, pred, flags, S, timeout,
-                           ctl, pubs, lists);
+                           ctl, words);
         return hipGetLastError();
     }
-    void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &pubs, &lists};
+    void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &words};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_lc<T, G, U>), dim3(nwg), dim3(T), args, 0, s);
 }
 
-hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, uint64_t* lists, bool plain,
+hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
                      hipStream_t s) {
     const int groups = (S + 3) / 4;
-    if (groups <= 1024) return launch_lc_t<1024, 1, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
-    if (groups <= 2048) return launch_lc_t<1024, 2, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
-    if (groups <= 4096) return launch_lc_t<1024, 4, 8>(a, nwg, S, timeout, pubs, lists, plain, s);
+    if (groups <= 1024) return launch_lc_t<1024, 1, 8>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 2048) return launch_lc_t<1024, 2, 8>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 4096) return launch_lc_t<1024, 4, 8>(a, nwg, S, timeout, words, plain, s);
     return hipErrorInvalidValue;
 }
 

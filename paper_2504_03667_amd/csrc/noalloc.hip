@@ -25,15 +25,14 @@ namespace {
 
 using namespace sssp;
 
-// Layout of the array: the control block, then exchange records for up to
-// 1024 workgroups (double-buffered), then the bucket lists (2 * nwg * S int32).
+// Layout of the array: the control block, then the gang's exchange memory
+// (records and lists, gang_words_bytes(nwg, S) bytes).  With slices of S
+// columns rounded up to a multiple of 4, nwg * S < n + 4 * nwg.
 constexpr size_t kCtlBytes = 8192;
-constexpr size_t kPubBytes = 2 * 1024 * 32;
 constexpr size_t kScratchBytes = SSSP_NOALLOC_SCRATCH_BYTES;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block outgrew its place in the fixed scratch");
-static_assert(sizeof(Pub) == 32, "records are 32 bytes");
-static_assert(kCtlBytes + kPubBytes + 2ull * (SSSP_NOALLOC_MAX_N + 16384) * 4 <= kScratchBytes,
-              "lists of the largest admitted n must fit");
+static_assert(kCtlBytes + gang_lists_offset(1024) + 2ull * (SSSP_NOALLOC_MAX_N + 4 * 1024) * 8 <= kScratchBytes,
+              "exchange memory of the largest admitted n must fit");
 
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
@@ -104,18 +103,15 @@ extern "C" int sssp_dense_solve_noalloc(const int32_t* W, int64_t ld, int32_t n,
         int nwg = 0, S = 0;
         rc = grid_shape(n, 0, false, false, cus, &nwg, &S);
         if (rc) return rc;
-        const size_t lists_bytes = 2ull * (size_t)nwg * (size_t)S * sizeof(int32_t);
-        if (nwg > 1024 || kCtlBytes + kPubBytes + lists_bytes > kScratchBytes)
+        if (nwg > 1024 || kCtlBytes + gang_words_bytes(nwg, S) > kScratchBytes)
             return set_error(SSSP_EUNSUPPORTED, "sssp_dense_solve_noalloc: launch shape exceeds the fixed scratch");
-        Pub* pubs = reinterpret_cast<Pub*>(base + kCtlBytes);
-        int32_t* lists = reinterpret_cast<int32_t*>(base + kCtlBytes + kPubBytes);
         // The array keeps whatever the last call left: clear the control block
-        // (barrier words, epoch, statistics) and the records this launch polls,
-        // with a fill kernel.  Stale list entries are never read before a record
-        // stamped by this launch points at them.
-        e = zero_fill(base, kCtlBytes + 2ull * (size_t)nwg * sizeof(Pub), s);
+        // (barrier words, epoch, statistics) and the stamped records this launch
+        // polls, with a fill kernel.  The tagged records and lists are cleared by
+        // the solve itself before its first exchange.
+        e = zero_fill(base, kCtlBytes + gang_recs_offset(nwg), s);
         if (e == hipSuccess)
-            e = launch_grid(a, nwg, S, grid_barrier_ticks(khz), pubs, lists, grid_launch_is_plain(), s);
+            e = launch_grid(a, nwg, S, grid_barrier_ticks(khz), base + kCtlBytes, grid_launch_is_plain(), s);
         if (e != hipSuccess) return set_error(SSSP_EDEVICE, "launch of the whole-GPU solve failed");
     }
     if (status) {

@@ -168,7 +168,7 @@ void gang_shape(const sssp_server_config& cfg, int nwg, int32_t n, int32_t metho
 }
 
 uint64_t footprint(int32_t method, int32_t parts, int32_t S) {
-    return item_scratch_bytes(method, parts, S, pub_size());
+    return item_scratch_bytes(method, parts, S);
 }
 
 // Latency mode: a gang query that nothing waits behind is split into narrower

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "engine.h"
+#include "sssp_internal.h"
 
 namespace sssp {
 
@@ -21,6 +22,8 @@ struct SharedSolve {
     uint32_t cnt[T];
     uint64_t rk;  // read_records results for the whole workgroup
     uint32_t rz, rm;
+    uint32_t late;        // a member's record did not arrive in time (read_records)
+    uint32_t stage_late;  // a bucket entry did not arrive in time (set once; the solve then ends)
     int32_t item;
     uint32_t flag;
 };
@@ -224,13 +227,28 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
     }
 }
 
-// Publish this workgroup's record for the next round: the lowest (dist, vertex)
+// Clear this member's tagged words (both slots of its record and of its list
+// region) before the solve's first exchange; see tag_word.
+template <int T>
+__device__ __forceinline__ void clear_tagged(uint64_t* __restrict__ recs, uint64_t* __restrict__ lists, int g, int nwg,
+                                             int S) {
+    if (threadIdx.x < 2 * kRecFields)
+        st_agent(rec_word(recs, nwg, threadIdx.x / kRecFields, threadIdx.x % kRecFields, g), (uint64_t)0);
+    for (int i = threadIdx.x; i < 2 * S; i += T) {
+        const int s = i >= S ? 1 : 0;
+        st_agent(&lists[((size_t)s * nwg + g) * S + (i - s * S)], (uint64_t)0);
+    }
+}
+
+// Publish this workgroup's record for exchange `tag`: the lowest (dist, vertex)
 // key among `cand` (one would-be dist per owned column, 0xffffffff = excluded),
-// the vertices of the slice at that dist, and the zero-weight hazard flag.
+// the vertices of the slice at that dist (list entries; none if `entries` is
+// false) and the zero-weight hazard flag, every word tagged.  Nothing waits for
+// the stores: readers check each word's tag.
 template <int T, int G>
 __device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layout& lo, int64_t col0,
-                                        uint32_t zero, Pub* __restrict__ pub, int32_t* __restrict__ list,
-                                        SharedSolve<T>& sh) {
+                                        uint32_t zero, bool entries, uint32_t tag, uint64_t* __restrict__ recs,
+                                        int nwg, int g, uint64_t* __restrict__ list, SharedSolve<T>& sh) {
     uint64_t key = kNoKey;
     if (lo.r == 0) {
 #pragma unroll
@@ -252,82 +270,179 @@ __device__ __forceinline__ void publish(const uint32_t (&cand)[G][4], const Layo
     }
     uint32_t total = 0;
     uint32_t rank = owner_excl_scan<T>(__popc(mask), total, lo.L, sh.red);
+    if (entries) {
+        stress_delay(2u * tag + 1u);
 #pragma unroll
-    for (int k = 0; k < G; ++k)
+        for (int k = 0; k < G; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (mask >> (4 * k + j) & 1u) st_agent(&list[rank++], (int32_t)(col0 + local_col(lo, k, j)));
+            for (int j = 0; j < 4; ++j)
+                if (mask >> (4 * k + j) & 1u)
+                    st_agent(&list[rank++], tag_word(tag, (uint32_t)(col0 + local_col(lo, k, j))));
+    }
     if (threadIdx.x == 0) {
-        st_agent(&pub->key, key);
-        st_agent(&pub->count, total);
-        st_agent(&pub->flags, zero);
+        stress_delay(2u * tag);
+        const uint32_t slot = (tag - 1) & 1;
+        st_agent(rec_word(recs, nwg, slot, kRecVert, g), tag_word(tag, (uint32_t)key));
+        st_agent(rec_word(recs, nwg, slot, kRecCnt, g), tag_word(tag, (total << 1) | (zero ? 1u : 0u)));
+        st_agent(rec_word(recs, nwg, slot, kRecDist, g), tag_word(tag, (uint32_t)(key >> 32)));
     }
 }
 
-// After an exchange, the gang's nwg records of one slot: K = the lowest key,
-// Z = the OR of the flags; for the round's bucket (records whose key has dist
-// d = K >> 32) each record's count and offset go to sh.cnt / sh.pre and their
-// sum to M.  Wave 0 does it alone (up to 4 contiguous records per lane) and
-// shares the results through LDS after one workgroup barrier; gangs of more
-// than 256 members take a block-wide path.
+// Bounded wait for a tagged word: returns it once it carries `tag`; on time-out
+// sets `late` and returns the last value read.
+__device__ __forceinline__ uint64_t wait_tag(const uint64_t* p, uint64_t w, uint32_t tag, long long timeout,
+                                             uint32_t& late) {
+    if (word_tag(w) == tag) return w;
+    const long long t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        w = ld_agent(p);
+        if (word_tag(w) == tag) return w;
+        if (wall_clock64() - t0 > timeout) {
+            late = 1;
+            return w;
+        }
+    }
+}
+
+// Exchange `tag` from the reader's side: waits for the gang's nwg tagged records
+// of its slot and reduces them.  `stamps` (the solve's first exchange only):
+// each member's tagged words are read only after its stamp, which it stored
+// once its cleared words were in place, has been seen (in an earlier poll, so
+// the tagged loads are issued after the stamp load returned).
+// K = the lowest key, Z = the OR of the hazard flags; for the round's bucket
+// (records whose key has dist d = K >> 32) each record's count and offset go to
+// sh.cnt / sh.pre and their sum to M.  Wave 0 polls and reduces (lane l takes
+// members l, l + 64, l + 128, l + 192, so that each load instruction reads 64
+// consecutive words) and shares the results through LDS after one workgroup
+// barrier; gangs of more than 256 members take a block-wide path.  Returns
+// false (K = no key, M = 0) if a member's record did not arrive within
+// `timeout` ticks.
 template <int T>
-__device__ __forceinline__ void read_records(const Pub* rp, int nwg, SharedSolve<T>& sh, uint64_t& K, uint32_t& Z,
-                                             uint32_t& M) {
+__device__ __forceinline__ bool read_records(uint64_t* recs, int nwg, uint32_t tag, long long timeout,
+                                             SharedSolve<T>& sh, uint64_t& K, uint32_t& Z, uint32_t& M,
+                                             const Pub* stamps, uint64_t stamp) {
+    const uint32_t slot = (tag - 1) & 1;
+    const uint64_t* rd = rec_word(recs, nwg, slot, kRecDist, 0);
+    const uint64_t* rv = rec_word(recs, nwg, slot, kRecVert, 0);
+    const uint64_t* rc = rec_word(recs, nwg, slot, kRecCnt, 0);
     if (nwg <= 4 * kWave) {
         if (threadIdx.x < kWave) {
-            const int q = (nwg + kWave - 1) / kWave;
-            const int i0 = (int)threadIdx.x * q;
+            const int l = (int)threadIdx.x;
             uint64_t key[4];
             uint32_t cnt[4];
-            uint64_t kmin = kNoKey;
-            uint32_t f = 0;
+            uint32_t want = 0, f = 0, late = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 key[k] = kNoKey;
                 cnt[k] = 0;
-                if (k < q && i0 + k < nwg) {
-                    key[k] = ld_agent(&rp[i0 + k].key);
-                    cnt[k] = ld_agent(&rp[i0 + k].count);
-                    f |= ld_agent(&rp[i0 + k].flags);
-                }
-                kmin = umin64(kmin, key[k]);
+                if (l + kWave * k < nwg) want |= 1u << k;
             }
+            // Every poll issues all of its loads before it checks any (member indexes
+            // clamped to the last member): a load per branch would be waited for
+            // before the next one, four round trips per poll instead of one.  Polls
+            // back off (up to ~0.1 us apart) so that members waiting through a long
+            // round do not load the memory system the others are streaming from.
+            const long long t0 = wall_clock64();
+            unsigned naps = 0;
+            if (stamps) {
+                uint32_t need = want;
+                for (;;) {
+                    uint64_t sv[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sv[k] = ld_agent(&stamps[min(l + kWave * k, nwg - 1)].stamp);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (sv[k] == stamp) need &= ~(1u << k);
+                    if (!need) break;
+                    if (wall_clock64() - t0 > timeout) {
+                        late = 1;
+                        want = 0;
+                        break;
+                    }
+                    for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
+                    naps = naps ? (naps < 4 ? naps << 1 : naps) : 1;
+                }
+            }
+            while (want) {
+                uint64_t a[4], b[4], c[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int m = min(l + kWave * k, nwg - 1);
+                    a[k] = ld_agent(&rd[m]);
+                    b[k] = ld_agent(&rv[m]);
+                    c[k] = ld_agent(&rc[m]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((want >> k & 1u) && word_tag(a[k]) == tag && word_tag(b[k]) == tag && word_tag(c[k]) == tag) {
+                        key[k] = make_key((uint32_t)a[k], (uint32_t)b[k]);
+                        cnt[k] = (uint32_t)c[k] >> 1;
+                        f |= (uint32_t)c[k] & 1u;
+                        want &= ~(1u << k);
+                    }
+                if (!want) break;
+                if (wall_clock64() - t0 > timeout) {
+                    late = 1;
+                    break;
+                }
+                for (unsigned i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(1);
+                naps = naps ? (naps < 4 ? naps << 1 : naps) : 1;
+            }
+            uint64_t kmin = kNoKey;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) kmin = umin64(kmin, key[k]);
             kmin = wave_min64(kmin);
             f = wave_or32(f);
+            late = wave_or32(late);
             const uint32_t d = (uint32_t)(kmin >> 32);
-            uint32_t local = 0;
+            // offsets in member order: a scan over each group of 64 members
+            uint32_t base = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (key[k] == kNoKey || (uint32_t)(key[k] >> 32) != d) cnt[k] = 0;
-                local += cnt[k];
-            }
-            const uint32_t inc = wave_scan32(local);
-            uint32_t run = inc - local;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (k < q && i0 + k < nwg) {
-                    sh.pre[i0 + k] = run;
-                    sh.cnt[i0 + k] = cnt[k];
-                    run += cnt[k];
+                if (kWave * k >= nwg) break;
+                const int m = l + kWave * k;
+                const uint32_t c = (key[k] == kNoKey || (uint32_t)(key[k] >> 32) != d) ? 0u : cnt[k];
+                const uint32_t inc = wave_scan32(c);
+                if (m < nwg) {
+                    sh.pre[m] = base + inc - c;
+                    sh.cnt[m] = c;
                 }
-            if (threadIdx.x == kWave - 1) {
-                sh.rk = kmin;
+                base += lane_value(inc, kWave - 1);
+            }
+            if (l == 0) {
+                sh.rk = late ? kNoKey : kmin;
                 sh.rz = f;
-                sh.rm = inc;
+                sh.rm = late ? 0u : base;
+                sh.late = late;
             }
         }
         __syncthreads();
-        K = sh.rk;
-        Z = sh.rz;
-        M = sh.rm;
-        return;
+        // the same in every thread: scalar registers
+        K = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(sh.rk >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)sh.rk);
+        Z = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.rz);
+        M = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.rm);
+        return __builtin_amdgcn_readfirstlane((int)sh.late) == 0;
     }
     uint64_t key = kNoKey;
-    uint32_t c = 0, f = 0;
+    uint32_t c = 0, f = 0, late = 0;
     if ((int)threadIdx.x < nwg) {
-        key = ld_agent(&rp[threadIdx.x].key);
-        c = ld_agent(&rp[threadIdx.x].count);
-        f = ld_agent(&rp[threadIdx.x].flags);
+        const int m = (int)threadIdx.x;
+        if (stamps) {
+            const long long t0 = wall_clock64();
+            while (ld_agent(&stamps[m].stamp) != stamp)
+                if (wall_clock64() - t0 > timeout) {
+                    late = 1;
+                    break;
+                }
+        }
+        const uint64_t a = wait_tag(&rd[m], ld_agent(&rd[m]), tag, timeout, late);
+        const uint64_t b = wait_tag(&rv[m], ld_agent(&rv[m]), tag, timeout, late);
+        const uint64_t w = wait_tag(&rc[m], ld_agent(&rc[m]), tag, timeout, late);
+        key = make_key((uint32_t)a, (uint32_t)b);
+        c = (uint32_t)w >> 1;
+        f = ((uint32_t)w & 1u) | (late << 1);
     }
     K = key;
     Z = f;
@@ -338,37 +453,43 @@ __device__ __forceinline__ void read_records(const Pub* rp, int nwg, SharedSolve
         sh.pre[threadIdx.x] = pre;
         sh.cnt[threadIdx.x] = c;
     }
+    if (threadIdx.x == 0) sh.late = (Z >> 1) & 1u;
     __syncthreads();
+    if (Z & 2u) {
+        K = kNoKey;
+        M = 0;
+        return false;
+    }
+    Z &= 1u;
+    return true;
 }
 
-// Entry e0 + threadIdx.x of the round's bucket, i.e. of the concatenation (in
+// Address of entry e of the round's bucket, i.e. of the concatenation (in
 // workgroup order) of the lists of the records whose minimum equals d.
 // sh.pre / sh.cnt hold each record's prefix offset and count.
 template <int T>
-__device__ __forceinline__ int32_t gather_entry(const SharedSolve<T>& sh, const int32_t* __restrict__ rl,
-                                                int nwg, int S, uint32_t e0, uint32_t M) {
-    const uint32_t e = e0 + threadIdx.x;
-    if (e >= M) return 0;
+__device__ __forceinline__ const uint64_t* entry_addr(const SharedSolve<T>& sh, const uint64_t* __restrict__ rl,
+                                                      int nwg, int S, uint32_t e) {
     int lo_i = 0, hi_i = nwg - 1;  // last record whose prefix is <= e (its count is non-zero)
     while (lo_i < hi_i) {
         const int mid = (lo_i + hi_i + 1) >> 1;
         if (sh.pre[mid] <= e) lo_i = mid;
         else hi_i = mid - 1;
     }
-    return ld_agent(&rl[(size_t)lo_i * S + (e - sh.pre[lo_i])]);
+    return &rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
 }
 
-// Rank g of a gang of nwg workgroups.  pubs: 2*nwg records, lists: 2*nwg*S
-// entries (double-buffered by barrier parity).  Returns false if a barrier
-// wait timed out.  `trace` (may be null) receives rank 0's round trace.  b0:
-// barriers the gang's words have already counted in this use (a solve that
-// follows another one on the same words continues the numbering).
+// Rank g of a gang of nwg workgroups.  gw: the gang's exchange memory (see
+// gang_words_bytes).  Returns false if a wait timed out.  `trace` (may be null)
+// receives rank 0's round trace.  b0: exchanges the gang's words have already
+// counted in this use (a solve that follows another one on the same words
+// continues the numbering); epoch: unique to this use of the words (stamps of
+// the first exchange).
 template <int T, int G, int U, typename E, bool NT = false>
 __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                            int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
-                           int S, int g, int nwg, long long timeout, Bar* bw, Pub* __restrict__ pubs,
-                           int32_t* __restrict__ lists, SharedSolve<T>& sh, SolveStats& st, Ctl* trace,
-                           uint32_t epoch, uint32_t b0 = 0) {
+                           int S, int g, int nwg, long long timeout, GangWords gw, SharedSolve<T>& sh,
+                           SolveStats& st, Ctl* trace, uint32_t epoch, uint32_t b0 = 0) {
     static_assert(T == kCap, "one staged bucket entry per thread");
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
@@ -376,66 +497,34 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
     Cols<G, E> cs;
     init_cols(cs, lo, col0, width, src);
     clear_merge<T>(sh.mrg, 4 * T);
+    auto list_of = [&](uint32_t x, int m) { return gw.lists + ((size_t)((x - 1) & 1) * nwg + m) * S; };
 
-    // initial record: the committed state (dist[src] = 0)
+    uint32_t b = b0;  // exchanges passed
+    bool ok = true;
+    // Clear this member's tagged words, then stamp its record for the first
+    // exchange (b0 + 1) once they are in place: readers take its tagged words
+    // only after seeing that stamp (read_records).
+    clear_tagged<T>(gw.recs, gw.lists, g, nwg, S);
+    // the same in every thread (it comes from a load): a scalar register
+    const uint64_t stamp1 = exchange_stamp((uint32_t)__builtin_amdgcn_readfirstlane((int)epoch), b0 + 1);
+    const Pub* stamps1 = gw.pubs + (size_t)(b0 & 1) * nwg;
+    if (threadIdx.x == 0) sh.stage_late = 0u;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        stress_delay((uint32_t)(stamp1 ^ (stamp1 >> 29)));
+        __builtin_amdgcn_s_waitcnt(0);
+        st_agent(&gw.pubs[(size_t)(b0 & 1) * nwg + g].stamp, stamp1);
+    }
+    // The first round's bucket, {src} at distance 0, is the same in every
+    // member's view: no exchange precedes it.
+    uint32_t d = 0, u0 = (uint32_t)src, M = 1;
+    bool first = true;
     uint32_t cand[G][4];
-#pragma unroll
-    for (int k = 0; k < G; ++k)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
-    uint32_t b = b0;  // barriers passed
-    publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)(b & 1) * nwg + g], &lists[((size_t)(b & 1) * nwg + g) * S], sh);
-    ++b;
-    bool ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
-
-    bool pending = false;
-    uint32_t pd = 0, pu0 = 0, pbucket = 0, pM = 0;
-    while (ok) {
-        const int slot = (b - 1) & 1;
-        const Pub* rp = pubs + (size_t)slot * nwg;
-        const int32_t* rl = lists + (size_t)slot * nwg * S;
-        uint64_t K;
-        uint32_t Z, M_rec;
-        read_records<T>(rp, nwg, sh, K, Z, M_rec);
-        if (pending) {
-            pending = false;
-            if (Z) {
-                // a fused round read a zero-weight edge out of its bucket: discard it
-                // and settle only the bucket's lowest-index vertex (one literal step)
-                ++st.fallbacks;
-                st.status |= kStatusZeroFallback;
-                reset_best(cs);
-                if (threadIdx.x == 0) sh.list[0] = (int32_t)pu0;
-                __syncthreads();
-                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
-                merge_partitions<T, G>(cs, lo, sh.mrg);
-                if (lo.r == 0) st.status |= commit_fused(cs, pd, owner_bit(lo, (int64_t)pu0 - col0, width));
-                else reset_best(cs);
-                st.settled += 1;
-#pragma unroll
-                for (int k = 0; k < G; ++k)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
-                const int ns = b & 1;
-                publish<T, G>(cand, lo, col0, 0u, &pubs[(size_t)ns * nwg + g],
-                              &lists[((size_t)ns * nwg + g) * S], sh);
-                ++b;
-                ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
-                continue;
-            }
-            if (lo.r == 0) st.status |= commit_fused(cs, pd, pbucket);
-            else reset_best(cs);
-            st.settled += pM;
-        }
-        const uint32_t d = (uint32_t)(K >> 32);
-        if (K == kNoKey || d >= kInf) break;
-        const uint32_t u0 = (uint32_t)K;
+    for (;;) {
         ++st.rounds;
         const long long t_round = wall_clock64();
-
-        // the round's bucket: records whose local minimum equals d
-        uint32_t M;
         uint32_t bucket;
         if (literal) {
             M = 1;
@@ -445,16 +534,29 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
             stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
-            M = M_rec;  // sh.pre / sh.cnt hold the bucket's records (read_records)
             // stage the bucket chunk by chunk; the next chunk's entries are loaded
-            // while the current chunk's rows stream
-            int32_t nxt = gather_entry<T>(sh, rl, nwg, S, 0, M);
+            // while the current chunk's rows stream (the first round's one entry,
+            // the source, is not loaded)
+            const uint64_t* rl = list_of(b, 0);
+            uint64_t nxt = first ? tag_word(b, u0)
+                         : threadIdx.x < M ? ld_agent(entry_addr<T>(sh, rl, nwg, S, threadIdx.x)) : 0;
             for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
-                sh.list[threadIdx.x] = nxt;
+                const uint32_t e = e0 + threadIdx.x;
+                if (e < M) {
+                    uint32_t late = 0;
+                    if (word_tag(nxt) != b) nxt = wait_tag(entry_addr<T>(sh, rl, nwg, S, e), nxt, b, timeout, late);
+                    // a time-out stages a valid row; the solve then ends with the time-out status
+                    sh.list[threadIdx.x] = late ? (int32_t)u0 : (int32_t)(uint32_t)nxt;
+                    if (late) sh.stage_late = 1u;
+                }
                 __syncthreads();
-                if (e0 + kCap < M) nxt = gather_entry<T>(sh, rl, nwg, S, e0 + kCap, M);
+                if (e + kCap < M) nxt = ld_agent(entry_addr<T>(sh, rl, nwg, S, e + kCap));
                 stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
                 __syncthreads();
+            }
+            if (sh.stage_late) {
+                ok = false;
+                break;
             }
         }
         merge_partitions<T, G>(cs, lo, sh.mrg);
@@ -471,15 +573,44 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
             for (int j = 0; j < 4; ++j) cand[k][j] = would_be(cs, k, j, d, bucket, neg);
         st.status |= neg;
         const uint32_t zero = (!literal && lo.r == 0) ? zero_hazard(cs, d) : 0u;
-        const int ns = b & 1;
-        publish<T, G>(cand, lo, col0, zero, &pubs[(size_t)ns * nwg + g], &lists[((size_t)ns * nwg + g) * S], sh);
-        pending = true;
-        pd = d;
-        pu0 = u0;
-        pbucket = bucket;
-        pM = M;
         ++b;
-        ok = gang_exchange<T>(pubs + (size_t)((b - 1) & 1) * nwg, g, exchange_stamp(epoch, b), (uint32_t)nwg, timeout, sh.red);
+        publish<T, G>(cand, lo, col0, zero, !literal, b, gw.recs, nwg, g, list_of(b, g), sh);
+        uint64_t K;
+        uint32_t Z, M_rec;
+        ok = read_records<T>(gw.recs, nwg, b, timeout, sh, K, Z, M_rec, first ? stamps1 : nullptr, stamp1);
+        first = false;
+        if (!ok) break;
+        if (Z) {
+            // the fused round read a zero-weight edge out of its bucket: discard it
+            // and settle only the bucket's lowest-index vertex (one literal step)
+            ++st.fallbacks;
+            st.status |= kStatusZeroFallback;
+            reset_best(cs);
+            if (threadIdx.x == 0) sh.list[0] = (int32_t)u0;
+            __syncthreads();
+            stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
+            merge_partitions<T, G>(cs, lo, sh.mrg);
+            if (lo.r == 0) st.status |= commit_fused(cs, d, owner_bit(lo, (int64_t)u0 - col0, width));
+            else reset_best(cs);
+            st.settled += 1;
+#pragma unroll
+            for (int k = 0; k < G; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
+            ++b;
+            publish<T, G>(cand, lo, col0, 0u, !literal, b, gw.recs, nwg, g, list_of(b, g), sh);
+            ok = read_records<T>(gw.recs, nwg, b, timeout, sh, K, Z, M_rec, nullptr, 0);
+            if (!ok) break;
+        } else {
+            if (lo.r == 0) st.status |= commit_fused(cs, d, bucket);
+            else reset_best(cs);
+            st.settled += M;
+        }
+        d = (uint32_t)(K >> 32);
+        if (K == kNoKey || d >= kInf) break;
+        u0 = (uint32_t)K;
+        M = M_rec;
     }
     if (!ok) st.status |= kStatusTimeout;
     write_out(cs, lo, col0, width, dist, pred);

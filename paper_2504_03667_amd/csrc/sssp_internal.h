@@ -32,15 +32,16 @@ int max_single_n();
 // plain: ordinary launch of the same kernel, the grid already bounded by the
 // occupancy query (co-resident on an otherwise idle GPU), instead of a
 // cooperative launch; used for profiler runs.
-hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs,
-                       int32_t* lists, bool plain, hipStream_t s);
+// words: gang_words_bytes(nwg, S) bytes of exchange memory.
+hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+                       hipStream_t s);
 int max_grid_slice();
 int grid_occupancy(int slice, int* per_cu);
 
 // Label-correcting solve on a cooperative grid of nwg workgroups (slices of S
-// columns); lists: 2 * nwg * S 64-bit entries.
-hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, Pub* pubs, uint64_t* lists,
-                     bool plain, hipStream_t s);
+// columns); words: gang_words_bytes(nwg, S) bytes of exchange memory.
+hipError_t launch_lc(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+                     hipStream_t s);
 
 // Zeroes `bytes` (a multiple of 4) of device memory with a kernel on stream s.
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t s);
@@ -72,13 +73,37 @@ constexpr int32_t kMethodLabelCorrecting = 1;
 // matrices whose off-diagonal weights are all >= 1.
 constexpr int32_t kMethodGroup = 2;
 
-// Arena bytes of an item's exchange records and lists (0 for a Dijkstra item
-// solved by one workgroup).
-inline unsigned long long item_scratch_bytes(int32_t method, int32_t parts, int32_t S, size_t pub_bytes) {
+// Exchange memory of a gang of nwg workgroups with slices of S columns, one
+// block: 2 * nwg stamped records (Pub, 32 bytes), the tagged records (32 bytes
+// per member and slot, see rec_word), then 2 * nwg * S 64-bit list words
+// (tagged bucket entries of the Dijkstra rounds, or the label-correcting
+// frontier).  Both kinds of record and the lists are double-buffered by
+// exchange parity.
+constexpr size_t kPubBytes = 32;
+constexpr size_t kTRecBytes = 32;
+__host__ __device__ constexpr size_t gang_recs_offset(int nwg) { return 2 * (size_t)nwg * kPubBytes; }
+__host__ __device__ constexpr size_t gang_lists_offset(int nwg) {
+    return gang_recs_offset(nwg) + 2 * (size_t)nwg * kTRecBytes;
+}
+__host__ __device__ constexpr size_t gang_words_bytes(int nwg, int S) {
+    return gang_lists_offset(nwg) + 2 * (size_t)nwg * (size_t)S * sizeof(uint64_t);
+}
+
+struct GangWords {
+    Pub* pubs;
+    uint64_t* recs;
+    uint64_t* lists;
+};
+__host__ __device__ inline GangWords gang_words(char* base, int nwg) {
+    return GangWords{reinterpret_cast<Pub*>(base), reinterpret_cast<uint64_t*>(base + gang_recs_offset(nwg)),
+                     reinterpret_cast<uint64_t*>(base + gang_lists_offset(nwg))};
+}
+
+// Arena bytes of an item's exchange memory (0 for a Dijkstra item solved by
+// one workgroup).
+inline unsigned long long item_scratch_bytes(int32_t method, int32_t parts, int32_t S) {
     if (method == kMethodDijkstra && parts <= 1) return 0;
-    const unsigned long long entry = method == kMethodLabelCorrecting ? 8 : 4;
-    const unsigned long long b = 2ull * parts * pub_bytes + 2ull * parts * (unsigned long long)S * entry;
-    return (b + 255) & ~255ull;
+    return ((unsigned long long)gang_words_bytes(parts, S) + 255) & ~255ull;
 }
 
 // Ticket t of a batched launch is part parts[t].part of item parts[t].item;
@@ -114,7 +139,6 @@ hipError_t weight_range(const int32_t* W, int64_t ld, int32_t n, int32_t* d_out3
 hipError_t compact_copy(const int32_t* W, int64_t ld, int32_t n, void* C, int64_t ldc, int elem, hipStream_t s);
 
 size_t ctl_size();
-size_t pub_size();
 
 // Per-device counters of the read-ceiling kernel (diag.hip): freed (after a
 // device synchronisation) by sssp_release_all; their device bytes.

@@ -233,7 +233,7 @@ def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroup
                                             _tuning(threads, workgroups), _stream(stream)))
 
 
-SSSP_NOALLOC_SCRATCH_BYTES = 4 << 20
+SSSP_NOALLOC_SCRATCH_BYTES = 8 << 20
 SSSP_NOALLOC_MAX_N = 262144
 
 

@@ -4,7 +4,8 @@
 // by later queries and launches without being cleared, so no word that any
 // use of that memory stores may equal a stamp: this program checks, over the
 // boundary values and random samples of every field, that stamps have bit 63
-// set while list entries and records' other words at stamp offsets do not.
+// set while list entries, tagged words and records' other words at stamp
+// offsets do not, and that tagged words carry their tag.
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
@@ -59,13 +60,38 @@ int main() {
     CHECK(sizeof(Pub) == 32 && alignof(Pub) == 32);
     CHECK(offsetof(Pub, stamp) == 0);
     CHECK(offsetof(Pub, key) == 8);
-    // arena regions of batched items and served queries are multiples of 256 bytes, so
-    // every use places its records at 32-byte offsets of the shared memory
+    // tagged words (tag_word): the tag of exchange b is b, at most 2n + 1 < 2^31 for any
+    // matrix that fits in memory, so tagged words never have bit 63 either; a cleared
+    // word (0) carries tag 0, which no exchange uses (b >= 1)
+    CHECK(kRecFields * sizeof(uint64_t) == kTRecBytes);
+    CHECK(word_tag(0) == 0u);
+    for (int i = 0; i < 1000000; ++i) {
+        const uint32_t tag = 1u + (uint32_t)(rng() % 0x7fffffffu), v = (uint32_t)rng();
+        const uint64_t w = tag_word(tag, v);
+        CHECK(w >> 63 == 0u);
+        CHECK(word_tag(w) == tag && (uint32_t)w == v);
+        CHECK(w != exchange_stamp((uint32_t)rng(), (uint32_t)rng()));
+        if (failures > 10) break;
+    }
+    // a gang's exchange memory: stamped records, tagged records and lists, each region
+    // at a 32-byte offset, so every use places its stamps at 32-byte offsets; arena
+    // regions of batched items and served queries are multiples of 256 bytes
     for (int i = 0; i < 100000; ++i) {
-        const int32_t method = (int32_t)(rng() & 1), parts = 1 + (int32_t)(rng() % 1024),
+        const int32_t method = (int32_t)(rng() % 3), parts = 1 + (int32_t)(rng() % 1024),
                       S = 4 * (1 + (int32_t)(rng() % 4096));
-        const unsigned long long bytes = item_scratch_bytes(method, parts, S, sizeof(Pub));
-        CHECK(bytes % 256 == 0);
+        CHECK(gang_recs_offset(parts) % 32 == 0 && gang_lists_offset(parts) % 32 == 0);
+        CHECK(gang_recs_offset(parts) == 2 * (size_t)parts * sizeof(Pub));
+        CHECK(gang_lists_offset(parts) == gang_recs_offset(parts) + 2 * (size_t)parts * kTRecBytes);
+        // the tagged words of every (slot, field, member) lie inside the tagged-record region
+        uint64_t* recs = reinterpret_cast<uint64_t*>(gang_recs_offset(parts));
+        const size_t last = (size_t)(rec_word(recs, parts, 1, kRecFields - 1, parts - 1) - recs);
+        CHECK(last == 2 * (size_t)parts * kRecFields - 1);
+        CHECK(gang_words_bytes(parts, S) == gang_lists_offset(parts) + 16 * (size_t)parts * (size_t)S);
+        if (method != kMethodGroup) {
+            const unsigned long long bytes = item_scratch_bytes(method, parts, S);
+            CHECK(bytes % 256 == 0);
+            CHECK(bytes >= (method == kMethodDijkstra && parts <= 1 ? 0 : gang_words_bytes(parts, S)));
+        }
         if (failures > 10) break;
     }
     // lockstep-group records: whole 32-byte multiples, every word but the stamp

@@ -71,7 +71,12 @@ def test_plans_all_configurations(sp):
                 info = plan.info()
                 assert status & 3 == 0, (flags, cfg, status)
                 total = check_items(graphs, items, refs, cache)
-                assert stats[1] == total
+                print("plan", flags, cfg, "lc_instances", info["lc_instances"], "rows", stats[1], "settled", total,
+                      flush=True)
+                if info["lc_instances"] == 0:
+                    assert stats[1] == total, (flags, cfg, stats, total)
+                else:  # label-correcting items count rows streamed, every reachable row at least once
+                    assert stats[1] >= total, (flags, cfg, stats, total)
                 assert info["graph"] == 1
                 if cfg:
                     assert info["single_max_n"] == cfg["single_max_n"]
