@@ -396,24 +396,27 @@ __device__ __forceinline__ bool read_records(uint64_t* recs, int nwg, uint32_t t
             f = wave_or32(f);
             late = wave_or32(late);
             const uint32_t d = (uint32_t)(kmin >> 32);
-            // offsets in member order: a scan over each group of 64 members
-            uint32_t base = 0;
+            // The bucket is the concatenation of the bucket records' lists in
+            // position order, position 4 l + k holding member l + 64 k (see
+            // entry_addr): one scan over the lanes' sums.
+            uint32_t c[4], local = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (kWave * k >= nwg) break;
-                const int m = l + kWave * k;
-                const uint32_t c = (key[k] == kNoKey || (uint32_t)(key[k] >> 32) != d) ? 0u : cnt[k];
-                const uint32_t inc = wave_scan32(c);
-                if (m < nwg) {
-                    sh.pre[m] = base + inc - c;
-                    sh.cnt[m] = c;
-                }
-                base += lane_value(inc, kWave - 1);
+                c[k] = (key[k] == kNoKey || (uint32_t)(key[k] >> 32) != d) ? 0u : cnt[k];
+                local += c[k];
+            }
+            const uint32_t inc = wave_scan32(local);
+            uint32_t run = inc - local;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sh.pre[4 * l + k] = run;
+                sh.cnt[4 * l + k] = c[k];
+                run += c[k];
             }
             if (l == 0) {
                 sh.rk = late ? kNoKey : kmin;
                 sh.rz = f;
-                sh.rm = late ? 0u : base;
+                sh.rm = late ? 0u : lane_value(inc, kWave - 1);
                 sh.late = late;
             }
         }
@@ -464,19 +467,23 @@ __device__ __forceinline__ bool read_records(uint64_t* recs, int nwg, uint32_t t
     return true;
 }
 
-// Address of entry e of the round's bucket, i.e. of the concatenation (in
-// workgroup order) of the lists of the records whose minimum equals d.
-// sh.pre / sh.cnt hold each record's prefix offset and count.
+// Address of entry e of the round's bucket, the concatenation of the lists of
+// the records whose minimum equals d.  sh.pre / sh.cnt hold each position's
+// prefix offset and count; with at most 256 members (read_records' wave path)
+// position 4 l + k holds member l + 64 k (positions of absent members count 0),
+// otherwise position m holds member m.
 template <int T>
 __device__ __forceinline__ const uint64_t* entry_addr(const SharedSolve<T>& sh, const uint64_t* __restrict__ rl,
                                                       int nwg, int S, uint32_t e) {
-    int lo_i = 0, hi_i = nwg - 1;  // last record whose prefix is <= e (its count is non-zero)
+    const bool packed = nwg <= 4 * kWave;
+    int lo_i = 0, hi_i = packed ? 4 * kWave - 1 : nwg - 1;  // last position whose prefix is <= e
     while (lo_i < hi_i) {
         const int mid = (lo_i + hi_i + 1) >> 1;
         if (sh.pre[mid] <= e) lo_i = mid;
         else hi_i = mid - 1;
     }
-    return &rl[(size_t)lo_i * S + (e - sh.pre[lo_i])];
+    const int m = packed ? (lo_i & 3) * kWave + (lo_i >> 2) : lo_i;
+    return &rl[(size_t)m * S + (e - sh.pre[lo_i])];
 }
 
 // Rank g of a gang of nwg workgroups.  gw: the gang's exchange memory (see
