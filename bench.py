@@ -52,19 +52,19 @@ def parse():
     return ap.parse_args()
 
 
-def timed_solves(sp, torch, Wt, src, steps, warmup, flags=0):
+def timed_solves(sp, torch, Wt, src, steps, warmup, flags=0, balance=0):
     n = Wt.shape[0]
     dist = torch.empty(n, dtype=torch.int32, device=Wt.device)
     pred = torch.empty(n, dtype=torch.int32, device=Wt.device)
     for _ in range(warmup):
-        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags)
+        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags, balance=balance)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
         starts[i].record()
-        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags)
+        sp.sssp_dense_solve_ex(Wt, Wt.stride(0), n, src, dist, pred, flags, balance=balance)
         ends[i].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -529,6 +529,12 @@ def main():
              "round_rows": [t[1] for t in trace[:-1]], "round_us": round_us,
              "ms_per_solve": round(ms, 4), "entries_per_s": entries / (ms * 1e-3),
              "algorithmic_GBps": round(alg_bytes / (ms * 1e-3) / 1e9, 1)}
+    # the same solves without pair balancing of the large rounds (identical dist/pred)
+    unb = timed_solves(sp, torch, Wt, 0, max(3, args.steps // 2), 1, balance=-1)
+    if not torch.equal(unb["dist"], r["dist"]) or not torch.equal(unb["pred"], r["pred"]):
+        raise RuntimeError("dist/pred differ without pair balancing")
+    large["kernel_ms_without_pair_balance"] = round(sum(unb["kernel_ms"]) / len(unb["kernel_ms"]), 4)
+    del unb
     # literal mode once: one vertex per grid barrier (Algorithm 1 as printed)
     if not args.only_large:
         lit = timed_solves(sp, torch, Wt, 0, 1, 0, flags=sp.SSSP_FLAG_LITERAL)

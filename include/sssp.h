@@ -93,7 +93,10 @@ typedef struct sssp_tuning {
                               gang, 2..16 (0 = autotune, 1 = never; see sssp_batch_plan_create) */
     int32_t group_columns; /* batched plans: columns per member of such a gang, 512..4096, a multiple
                               of 4 (0 = with group_sources: 1024) */
-    int32_t reserved[2];
+    int32_t balance;       /* whole-GPU solve: pairs of workgroups share the rows of rounds of at
+                              least 8192 rows (0 = from n >= 32768, 1 = always, -1 = never); dist
+                              and pred do not depend on it */
+    int32_t reserved[1];
 } sssp_tuning;
 
 /* One solve of a batch: same meaning as the arguments of sssp_dense_solve_ex. */

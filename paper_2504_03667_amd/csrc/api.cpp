@@ -44,7 +44,7 @@ struct Scratch {
     int device = -1;
     hipStream_t stream = nullptr;
     Ctl* ctl = nullptr;
-    char* words = nullptr;  // exchange records and lists of the whole-GPU solves (gang_words_bytes)
+    char* words = nullptr;  // exchange records and lists of the whole-GPU solves (grid_words_bytes)
     size_t words_cap = 0;
     bool launched = false;
 };
@@ -263,13 +263,15 @@ int solve(const int32_t* W, int64_t ld, int32_t n, int32_t src, int32_t* dist, i
         rc = grid_shape(n, tuning && tuning->workgroups ? tuning->workgroups : 0, lc, lc && (flags & SSSP_FLAG_SINGLE),
                         di.cus, &nwg, &S);
         if (rc) return rc;
-        rc = ensure(sc, sc->words, sc->words_cap, gang_words_bytes(nwg, S), "exchange records and lists");
+        rc = ensure(sc, sc->words, sc->words_cap, grid_words_bytes(nwg, S), "exchange records and lists");
         if (rc) return rc;
         if (lc) {
             e = launch_lc(a, nwg, S, barrier_timeout_ticks(di), sc->words, plain_grid_launch(), stream);
             if (e != hipSuccess) return hip_fail(e, "cooperative launch(label-correcting solve)");
         } else {
-            e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->words, plain_grid_launch(), stream);
+            const int32_t bal = tuning ? tuning->balance : 0;
+            const bool balance = bal > 0 || (bal == 0 && n >= kGridBalanceMinN);
+            e = launch_grid(a, nwg, S, barrier_timeout_ticks(di), sc->words, plain_grid_launch(), balance, stream);
             if (e != hipSuccess) return hip_fail(e, "cooperative launch(whole-GPU solve)");
         }
     }

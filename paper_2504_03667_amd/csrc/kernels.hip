@@ -54,7 +54,10 @@ __global__ __launch_bounds__(T) void k_single(const int32_t* __restrict__ W, int
     }
 }
 
-template <int T, int G, int U>
+// BAL: pair balancing of large rounds (solve_gang); chosen by the launcher for
+// graphs large enough to have them, since its code costs the small rounds a few
+// registers.
+template <int T, int G, int U, bool BAL>
 __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64_t ld, int32_t n,
                                             int32_t src, int32_t* __restrict__ dist,
                                             int32_t* __restrict__ pred, uint32_t flags, int32_t S,
@@ -62,8 +65,8 @@ __global__ __launch_bounds__(T) void k_grid(const int32_t* __restrict__ W, int64
     SharedSolve<T>& sh = g_sh<T>;
     SolveStats st = {0, 0, 0, 0, 0};
     const uint32_t epoch = ld_agent(&ctl->epoch);
-    solve_gang<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
-                        blockIdx.x, gridDim.x, timeout, gang_words(words, gridDim.x), sh, st, ctl, epoch);
+    solve_gang<T, G, U, int32_t, true, BAL>(W, ld, n, src, dist, pred, (flags & kFlagVec) != 0, (flags & kFlagLiteral) != 0, S,
+                        blockIdx.x, gridDim.x, timeout, grid_words(words, gridDim.x, S), sh, st, ctl, epoch);
     finish_launch(ctl, st, blockIdx.x == 0);
 }
 
@@ -99,7 +102,7 @@ __device__ __attribute__((noinline)) SolveStats gang_variant(BatchItem I, int pa
     SolveStats st = {0, 0, 0, 0, 0};
     solve_gang<T, G, rows_in_flight<E>(), E>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
                                             I.vec != 0, literal, I.S, part, I.parts, timeout,
-                                            gang_words(arena + I.scratch_off, I.parts), g_sh<T>, st, nullptr, epoch);
+                                            gang_words(arena + I.scratch_off, I.parts, I.S), g_sh<T>, st, nullptr, epoch);
     if (threadIdx.x == 0) gang_leave(bw, (uint32_t)I.parts);
     return st;
 }
@@ -111,7 +114,7 @@ template <int T, int G, typename E>
 __device__ __attribute__((noinline)) SolveStats lc_variant(BatchItem I, int part, long long timeout, Bar* bw,
                                                            char* arena, uint32_t epoch) {
     SolveStats st = {0, 0, 0, 0, 0};
-    const GangWords gw = gang_words(arena + I.scratch_off, I.parts);
+    const GangWords gw = gang_words(arena + I.scratch_off, I.parts, I.S);
     uint32_t b = 0;
     const int r = solve_lc<T, G, 8, E, false>(static_cast<const E*>(I.W), I.ld, I.n, I.src, I.dist, I.pred,
                                               I.vec != 0, I.S, part, I.parts, timeout, bw, gw.pubs, gw.lists, g_sh<T>,
@@ -415,7 +418,7 @@ hipError_t launch_single(const SolveArgs& a, int threads, hipStream_t s) {
 
 int max_single_n() { return 4 * 4 * 1024; }
 
-template <int T, int G, int U>
+template <int T, int G, int U, bool BAL>
 static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
                                 hipStream_t s) {
     const int32_t* W = a.W;
@@ -426,21 +429,27 @@ static hipError_t launch_grid_t(const SolveArgs& a, int nwg, int S, long long ti
     uint32_t flags = a.flags;
     Ctl* ctl = a.ctl;
     if (plain) {
-        hipLaunchKernelGGL((k_grid<T, G, U>), dim3(nwg), dim3(T), 0, s, W, ld, n, src, dist, pred, flags, S,
+        hipLaunchKernelGGL((k_grid<T, G, U, BAL>), dim3(nwg), dim3(T), 0, s, W, ld, n, src, dist, pred, flags, S,
                            timeout, ctl, words);
         return hipGetLastError();
     }
     void* args[] = {&W, &ld, &n, &src, &dist, &pred, &flags, &S, &timeout, &ctl, &words};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid<T, G, U>), dim3(nwg),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_grid<T, G, U, BAL>), dim3(nwg),
                                       dim3(T), args, 0, s);
 }
 
-hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain, bool balance,
                        hipStream_t s) {
     const int groups = (S + 3) / 4;
-    if (groups <= 1024) return launch_grid_t<1024, 1, 8>(a, nwg, S, timeout, words, plain, s);
-    if (groups <= 2048) return launch_grid_t<1024, 2, 8>(a, nwg, S, timeout, words, plain, s);
-    if (groups <= 4096) return launch_grid_t<1024, 4, 8>(a, nwg, S, timeout, words, plain, s);
+    if (!balance) {
+        if (groups <= 1024) return launch_grid_t<1024, 1, 8, false>(a, nwg, S, timeout, words, plain, s);
+        if (groups <= 2048) return launch_grid_t<1024, 2, 8, false>(a, nwg, S, timeout, words, plain, s);
+        if (groups <= 4096) return launch_grid_t<1024, 4, 8, false>(a, nwg, S, timeout, words, plain, s);
+        return hipErrorInvalidValue;
+    }
+    if (groups <= 1024) return launch_grid_t<1024, 1, 8, true>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 2048) return launch_grid_t<1024, 2, 8, true>(a, nwg, S, timeout, words, plain, s);
+    if (groups <= 4096) return launch_grid_t<1024, 4, 8, true>(a, nwg, S, timeout, words, plain, s);
     return hipErrorInvalidValue;
 }
 
@@ -448,9 +457,10 @@ int max_grid_slice() { return 4 * 4 * 1024; }
 
 int grid_occupancy(int slice, int* per_cu) {
     const int groups = (slice + 3) / 4;
-    const void* f = groups <= 1024 ? reinterpret_cast<const void*>(&k_grid<1024, 1, 8>)
-                  : groups <= 2048 ? reinterpret_cast<const void*>(&k_grid<1024, 2, 8>)
-                                   : reinterpret_cast<const void*>(&k_grid<1024, 4, 8>);
+    // both balancing variants have the same launch bounds and LDS
+    const void* f = groups <= 1024 ? reinterpret_cast<const void*>(&k_grid<1024, 1, 8, true>)
+                  : groups <= 2048 ? reinterpret_cast<const void*>(&k_grid<1024, 2, 8, true>)
+                                   : reinterpret_cast<const void*>(&k_grid<1024, 4, 8, true>);
     return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 1024, 0);
 }
 

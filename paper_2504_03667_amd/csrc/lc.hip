@@ -20,7 +20,7 @@ __global__ __launch_bounds__(T) void k_lc(const int32_t* __restrict__ W, int64_t
     uint32_t b = 0;
     const bool vec = (flags & kFlagVec) != 0;
     const uint32_t epoch = ld_agent(&ctl->epoch);
-    const GangWords gw = gang_words(words, gridDim.x);
+    const GangWords gw = grid_words(words, gridDim.x, S);
     const int r = solve_lc<T, G, U, int32_t, true>(W, ld, n, src, dist, pred, vec, S, blockIdx.x, gridDim.x, timeout,
                                                    &ctl->b, gw.pubs, gw.lists, sh, g_lc<T>, st, b, epoch, ctl);
     if (r == kLcTimeout) {

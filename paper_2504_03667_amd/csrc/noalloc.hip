@@ -26,13 +26,14 @@ namespace {
 using namespace sssp;
 
 // Layout of the array: the control block, then the gang's exchange memory
-// (records and lists, gang_words_bytes(nwg, S) bytes).  With slices of S
-// columns rounded up to a multiple of 4, nwg * S < n + 4 * nwg.
+// (records, lists and partial keys, grid_words_bytes(nwg, S) bytes: 24 bytes
+// per slice column beyond the records).  With slices of S columns rounded up
+// to a multiple of 4, nwg * S < n + 4 * nwg.
 constexpr size_t kCtlBytes = 8192;
 constexpr size_t kScratchBytes = SSSP_NOALLOC_SCRATCH_BYTES;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block outgrew its place in the fixed scratch");
-static_assert(kCtlBytes + gang_lists_offset(1024) + 2ull * (SSSP_NOALLOC_MAX_N + 4 * 1024) * 8 <= kScratchBytes,
-              "exchange memory of the largest admitted n must fit");
+static_assert(kCtlBytes + grid_words_bytes(1024, 0) + 24ull * (SSSP_NOALLOC_MAX_N + 4 * 1024) <= kScratchBytes,
+              "exchange memory of the largest admitted n must fit (24 bytes per slice column)");
 
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
@@ -103,7 +104,7 @@ extern "C" int sssp_dense_solve_noalloc(const int32_t* W, int64_t ld, int32_t n,
         int nwg = 0, S = 0;
         rc = grid_shape(n, 0, false, false, cus, &nwg, &S);
         if (rc) return rc;
-        if (nwg > 1024 || kCtlBytes + gang_words_bytes(nwg, S) > kScratchBytes)
+        if (nwg > 1024 || kCtlBytes + grid_words_bytes(nwg, S) > kScratchBytes)
             return set_error(SSSP_EUNSUPPORTED, "sssp_dense_solve_noalloc: launch shape exceeds the fixed scratch");
         // The array keeps whatever the last call left: clear the control block
         // (barrier words, epoch, statistics) and the stamped records this launch
@@ -111,7 +112,8 @@ extern "C" int sssp_dense_solve_noalloc(const int32_t* W, int64_t ld, int32_t n,
         // the solve itself before its first exchange.
         e = zero_fill(base, kCtlBytes + gang_recs_offset(nwg), s);
         if (e == hipSuccess)
-            e = launch_grid(a, nwg, S, grid_barrier_ticks(khz), base + kCtlBytes, grid_launch_is_plain(), s);
+            e = launch_grid(a, nwg, S, grid_barrier_ticks(khz), base + kCtlBytes, grid_launch_is_plain(),
+                            n >= kGridBalanceMinN, s);
         if (e != hipSuccess) return set_error(SSSP_EDEVICE, "launch of the whole-GPU solve failed");
     }
     if (status) {

@@ -12,6 +12,8 @@
 namespace sssp {
 
 constexpr int kCap = 1024;  // bucket rows staged in LDS per chunk
+constexpr uint32_t kPairChunks = 8;  // chunks from which a round is balanced within pairs (solve_gang)
+constexpr uint32_t kPairUnit = 256;  // rows per claim unit of a balanced round
 
 template <int T>
 struct SharedSolve {
@@ -22,6 +24,7 @@ struct SharedSolve {
     uint32_t cnt[T];
     uint64_t rk;  // read_records results for the whole workgroup
     uint32_t rz, rm;
+    uint32_t claim[2];    // chunk claims of a balanced round, broadcast by thread 0
     uint32_t late;        // a member's record did not arrive in time (read_records)
     uint32_t stage_late;  // a bucket entry did not arrive in time (set once; the solve then ends)
     int32_t item;
@@ -230,10 +233,14 @@ __device__ __forceinline__ void finish_launch(Ctl* ctl, const SolveStats& st, bo
 // Clear this member's tagged words (both slots of its record and of its list
 // region) before the solve's first exchange; see tag_word.
 template <int T>
-__device__ __forceinline__ void clear_tagged(uint64_t* __restrict__ recs, uint64_t* __restrict__ lists, int g, int nwg,
+__device__ __forceinline__ void clear_tagged(uint64_t* __restrict__ recs, uint64_t* __restrict__ lists,
+                                             uint32_t* __restrict__ ctr, uint64_t* __restrict__ done, int g, int nwg,
                                              int S) {
     if (threadIdx.x < 2 * kRecFields)
         st_agent(rec_word(recs, nwg, threadIdx.x / kRecFields, threadIdx.x % kRecFields, g), (uint64_t)0);
+    if (threadIdx.x == 2 * kRecFields) st_agent(&done[2 * g], (uint64_t)0);
+    if (threadIdx.x == 2 * kRecFields + 1) st_agent(&ctr[4 * g], 0u);
+    if (threadIdx.x == 2 * kRecFields + 2) st_agent(&ctr[4 * g + 1], 0u);
     for (int i = threadIdx.x; i < 2 * S; i += T) {
         const int s = i >= S ? 1 : 0;
         st_agent(&lists[((size_t)s * nwg + g) * S + (i - s * S)], (uint64_t)0);
@@ -492,12 +499,33 @@ __device__ __forceinline__ const uint64_t* entry_addr(const SharedSolve<T>& sh, 
 // counted in this use (a solve that follows another one on the same words
 // continues the numbering); epoch: unique to this use of the words (stamps of
 // the first exchange).
-template <int T, int G, int U, typename E, bool NT = false>
+//
+// BAL: pair balancing of large rounds.  Equal slices do not take equal time
+// (workgroups on some XCDs stream measurably slower), and a round lasts as long
+// as its slowest member.  In a round of at least kPairChunks chunks, members g
+// and g ^ 1 claim the rows of their own slice from the front of a counter, a
+// staging chunk (kCap rows) at a time; one that runs out claims the partner's
+// remaining rows from the back, kPairUnit rows at a time, streams them over the
+// partner's columns, then hands the partial minima over (partial keys, then a
+// tagged done word once they are in memory).  The counter word counts units of
+// kPairUnit rows, front claims in its low 16 bits and back claims in its high
+// 16 bits; the atomic adds serialise the claims, a claim made when front +
+// back < units is valid, a front claim stops at the back claims made before it,
+// and later back claims see its whole increment, so no row is taken twice or
+// left out.  Claims are made two ahead so that their latency hides behind the
+// streaming; the helper's claims from the back do not wait for the rows the
+// owner has reserved at the front.  Each member has two
+// counters (round parity) and resets one only after reading the exchange that
+// follows the round that used it, when both members' claims on it have
+// returned, and before its next publish (the partner claims on it again only
+// after that publish).
+template <int T, int G, int U, typename E, bool NT = false, bool BAL = false>
 __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, int32_t n, int32_t src,
                            int32_t* __restrict__ dist, int32_t* __restrict__ pred, bool vec, bool literal,
                            int S, int g, int nwg, long long timeout, GangWords gw, SharedSolve<T>& sh,
                            SolveStats& st, Ctl* trace, uint32_t epoch, uint32_t b0 = 0) {
     static_assert(T == kCap, "one staged bucket entry per thread");
+    static_assert(!BAL || sizeof(E) == 4, "pair balancing keeps 64-bit keys");
     const int64_t col0 = (int64_t)g * S;
     const int width = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - col0));
     const Layout lo = make_layout<T>(S);
@@ -511,7 +539,12 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
     // Clear this member's tagged words, then stamp its record for the first
     // exchange (b0 + 1) once they are in place: readers take its tagged words
     // only after seeing that stamp (read_records).
-    clear_tagged<T>(gw.recs, gw.lists, g, nwg, S);
+    clear_tagged<T>(gw.recs, gw.lists, gw.ctr, gw.done, g, nwg, S);
+    // pair balancing: the partner, counter slots that a round has used and not
+    // yet reset, and the value of the last reset (used before the next publish)
+    const int pg = g ^ 1;
+    const bool paired = BAL && pg < nwg && lo.P > 1;
+    uint32_t used = 0, reset_old = 0;
     // the same in every thread (it comes from a load): a scalar register
     const uint64_t stamp1 = exchange_stamp((uint32_t)__builtin_amdgcn_readfirstlane((int)epoch), b0 + 1);
     const Pub* stamps1 = gw.pubs + (size_t)(b0 & 1) * nwg;
@@ -541,32 +574,146 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
             stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, 1);
         } else {
             bucket = bucket_mask(cs, d);
-            // stage the bucket chunk by chunk; the next chunk's entries are loaded
-            // while the current chunk's rows stream (the first round's one entry,
-            // the source, is not loaded)
             const uint64_t* rl = list_of(b, 0);
-            uint64_t nxt = first ? tag_word(b, u0)
-                         : threadIdx.x < M ? ld_agent(entry_addr<T>(sh, rl, nwg, S, threadIdx.x)) : 0;
-            for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
-                const uint32_t e = e0 + threadIdx.x;
-                if (e < M) {
+            // entry e of the bucket into sh.list[threadIdx.x]; w: its word as loaded
+            auto stage = [&](uint32_t e, uint64_t w) {
+                uint32_t late = 0;
+                if (word_tag(w) != b) w = wait_tag(entry_addr<T>(sh, rl, nwg, S, e), w, b, timeout, late);
+                // a time-out stages a valid row; the solve then ends with the time-out status
+                sh.list[threadIdx.x] = late ? (int32_t)u0 : (int32_t)(uint32_t)w;
+                if (late) sh.stage_late = 1u;
+            };
+            const uint32_t C = (M + kCap - 1) / kCap;
+            if (paired && C >= kPairChunks) {
+                const uint32_t slot = b & 1;
+                const uint32_t tag = b + 1;  // the exchange this round publishes
+                key_t<E>* keep = reinterpret_cast<key_t<E>*>(sh.mrg + 2 * T);
+                uint32_t own = 0;
+                for (int side = 0; side < 2; ++side) {
+                    const int m = side ? pg : g;
+                    const int64_t c0 = (int64_t)m * S;
+                    const int wd = (int)max((int64_t)0, min((int64_t)S, (int64_t)n - c0));
+                    uint32_t* ctr = &gw.ctr[4 * m + slot];
+                    // claims count units of kPairUnit rows: the owner takes a staging
+                    // chunk (kCap rows) at a time from the front, the helper one unit at
+                    // a time from the back
+                    constexpr uint32_t kChunkUnits = (uint32_t)kCap / kPairUnit;
+                    const uint32_t units = (M + kPairUnit - 1) / kPairUnit;
+                    uint32_t left = units;  // units unclaimed when the last decoded claim was made
+                    // rows [begin, begin + count) of a claim of `n` units (the counter
+                    // before it in `old`); count 0 if it came too late.  A front claim stops
+                    // at the back claims made before it; later back claims see its whole
+                    // increment and stay clear.
+                    auto rows_of = [&](uint32_t old, uint32_t nu, uint32_t& begin) -> uint32_t {
+                        const uint32_t f = old & 0xffffu, h = old >> 16;
+                        begin = 0;
+                        left = f + h >= units ? 0u : units - f - h;
+                        if (!left) return 0u;
+                        const uint32_t u0 = side ? units - 1 - h : f;
+                        const uint32_t u1 = side ? u0 + 1 : min(f + nu, units - h);
+                        begin = u0 * kPairUnit;
+                        return min(u1 * kPairUnit, M) - begin;
+                    };
+                    // the owner claims whole staging chunks, single units once few are
+                    // left (so that it reserves little for the helper to wait behind);
+                    // the helper always claims single units
+                    auto units_next = [&]() { return side || left <= 3 * kChunkUnits ? 1u : kChunkUnits; };
+                    auto inc_of = [&](uint32_t nu) { return side ? 0x10000u : nu; };
+                    if (side == 1) {
+                        // keep this member's candidates while it streams rows for the partner
+                        merge_partitions<T, G>(cs, lo, sh.mrg);
+                        if (lo.r == 0)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) keep[j * lo.L + lo.c] = cs.best[0][j];
+                        reset_best(cs);
+                    }
+                    const uint32_t nu0 = units_next();
+                    if (threadIdx.x == 0) {
+                        if (side == 0) stress_delay(4u * tag + 3u);  // late starters: partners steal
+                        sh.claim[0] = __hip_atomic_fetch_add(ctr, inc_of(nu0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        sh.claim[1] = __hip_atomic_fetch_add(ctr, inc_of(nu0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    __syncthreads();
+                    uint32_t kb = 0, nb = 0;
+                    uint32_t kcnt = rows_of((uint32_t)__builtin_amdgcn_readfirstlane((int)sh.claim[0]), nu0, kb);
+                    uint32_t ncnt = rows_of((uint32_t)__builtin_amdgcn_readfirstlane((int)sh.claim[1]), nu0, nb);
+                    uint32_t chunks = 0;  // rows streamed on this side
+                    uint64_t w = 0;
+                    if (threadIdx.x < kcnt) w = ld_agent(entry_addr<T>(sh, rl, nwg, S, kb + threadIdx.x));
+                    while (kcnt) {
+                        if (threadIdx.x < kcnt) stage(kb + threadIdx.x, w);
+                        __syncthreads();
+                        uint32_t a = 0xffffffffu;  // no further claim: nothing is left after the next one
+                        const uint32_t nua = units_next();
+                        if (ncnt) {
+                            if (threadIdx.x < ncnt) w = ld_agent(entry_addr<T>(sh, rl, nwg, S, nb + threadIdx.x));
+                            if (threadIdx.x == 0)
+                                a = __hip_atomic_fetch_add(ctr, inc_of(nua), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        stream_rows<G, U, E, NT>(cs, lo, W, ld, c0, wd, vec, sh.list, (int)kcnt);
+                        if (threadIdx.x == 0) sh.claim[0] = a;
+                        __syncthreads();
+                        chunks += kcnt;
+                        kb = nb;
+                        kcnt = ncnt;
+                        ncnt = rows_of((uint32_t)__builtin_amdgcn_readfirstlane((int)sh.claim[0]), nua, nb);
+                    }
+                    if (side == 0) {
+                        own = chunks;
+                        continue;
+                    }
+                    if (chunks) {
+                        // the partner's share of its own columns: partial minima, then the
+                        // tagged done word once they are in memory
+                        merge_partitions<T, G>(cs, lo, sh.mrg);
+                        if (lo.r == 0)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                st_agent(&gw.part[(size_t)pg * S + 4 * lo.c + j], (uint64_t)cs.best[0][j]);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __syncthreads();
+                        if (threadIdx.x == 0) st_agent(&gw.done[2 * pg], tag_word(tag, chunks));
+                    }
+                    // back to this member's own candidates
+                    if (lo.r == 0) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) cs.best[0][j] = keep[j * lo.L + lo.c];
+                    } else {
+                        reset_best(cs);
+                    }
+                }
+                if (own < M && lo.r == 0) {
+                    // the partner streamed the rest of this member's chunks: its partial minima
                     uint32_t late = 0;
-                    if (word_tag(nxt) != b) nxt = wait_tag(entry_addr<T>(sh, rl, nwg, S, e), nxt, b, timeout, late);
-                    // a time-out stages a valid row; the solve then ends with the time-out status
-                    sh.list[threadIdx.x] = late ? (int32_t)u0 : (int32_t)(uint32_t)nxt;
+                    (void)wait_tag(&gw.done[2 * g], ld_agent(&gw.done[2 * g]), tag, timeout, late);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        cs.best[0][j] = key_min(cs.best[0][j], (key_t<E>)ld_agent(&gw.part[(size_t)g * S + 4 * lo.c + j]));
                     if (late) sh.stage_late = 1u;
                 }
-                __syncthreads();
-                if (e + kCap < M) nxt = ld_agent(entry_addr<T>(sh, rl, nwg, S, e + kCap));
-                stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list, (int)min((uint32_t)kCap, M - e0));
-                __syncthreads();
-            }
-            if (sh.stage_late) {
-                ok = false;
-                break;
+                used |= 1u << slot;
+            } else {
+                // stage the bucket chunk by chunk; the next chunk's entries are loaded
+                // while the current chunk's rows stream (the first round's one entry,
+                // the source, is not loaded)
+                uint64_t nxt = first ? tag_word(b, u0)
+                             : threadIdx.x < M ? ld_agent(entry_addr<T>(sh, rl, nwg, S, threadIdx.x)) : 0;
+                for (uint32_t e0 = 0; e0 < M; e0 += kCap) {
+                    const uint32_t e = e0 + threadIdx.x;
+                    if (e < M) stage(e, nxt);
+                    __syncthreads();
+                    if (e + kCap < M) nxt = ld_agent(entry_addr<T>(sh, rl, nwg, S, e + kCap));
+                    stream_rows<G, U, E, NT>(cs, lo, W, ld, col0, width, vec, sh.list,
+                                             (int)min((uint32_t)kCap, M - e0));
+                    __syncthreads();
+                }
             }
         }
         merge_partitions<T, G>(cs, lo, sh.mrg);
+        if (sh.stage_late) {
+            ok = false;
+            break;
+        }
         if (trace && g == 0 && threadIdx.x == 0 && st.rounds <= (unsigned long long)kTraceCap) {
             trace->trace_t[st.rounds - 1] = t_round;
             trace->trace_m[st.rounds - 1] = M;
@@ -581,12 +728,20 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
         st.status |= neg;
         const uint32_t zero = (!literal && lo.r == 0) ? zero_hazard(cs, d) : 0u;
         ++b;
+        if (BAL) asm volatile("" ::"v"(reset_old));  // a counter reset has completed before this publish
         publish<T, G>(cand, lo, col0, zero, !literal, b, gw.recs, nwg, g, list_of(b, g), sh);
         uint64_t K;
         uint32_t Z, M_rec;
         ok = read_records<T>(gw.recs, nwg, b, timeout, sh, K, Z, M_rec, first ? stamps1 : nullptr, stamp1);
         first = false;
         if (!ok) break;
+        if (BAL && (used >> ((b - 1) & 1) & 1u)) {
+            // every claim on the counter slot of the round just published has returned
+            if (threadIdx.x == 0)
+                reset_old = __hip_atomic_exchange(&gw.ctr[4 * g + ((b - 1) & 1)], 0u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            used &= ~(1u << ((b - 1) & 1));
+        }
         if (Z) {
             // the fused round read a zero-weight edge out of its bucket: discard it
             // and settle only the bucket's lowest-index vertex (one literal step)
@@ -606,6 +761,7 @@ __device__ __forceinline__ bool solve_gang(const E* __restrict__ W, int64_t ld, 
                 for (int j = 0; j < 4; ++j)
                     cand[k][j] = (cs.vis >> (4 * k + j) & 1u) ? 0xffffffffu : cs.dist[k][j];
             ++b;
+            if (BAL) asm volatile("" ::"v"(reset_old));
             publish<T, G>(cand, lo, col0, 0u, !literal, b, gw.recs, nwg, g, list_of(b, g), sh);
             ok = read_records<T>(gw.recs, nwg, b, timeout, sh, K, Z, M_rec, nullptr, 0);
             if (!ok) break;

@@ -32,11 +32,15 @@ int max_single_n();
 // plain: ordinary launch of the same kernel, the grid already bounded by the
 // occupancy query (co-resident on an otherwise idle GPU), instead of a
 // cooperative launch; used for profiler runs.
-// words: gang_words_bytes(nwg, S) bytes of exchange memory.
-hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain,
+// words: grid_words_bytes(nwg, S) bytes of exchange memory.  balance: pair
+// balancing of large rounds (see solve_gang).
+hipError_t launch_grid(const SolveArgs& a, int nwg, int S, long long timeout, char* words, bool plain, bool balance,
                        hipStream_t s);
 int max_grid_slice();
 int grid_occupancy(int slice, int* per_cu);
+// Graphs from which the whole-GPU kernel balances large rounds within pairs
+// of workgroups by default (rounds of at least 8 Ki rows become likely).
+constexpr int32_t kGridBalanceMinN = 32768;
 
 // Label-correcting solve on a cooperative grid of nwg workgroups (slices of S
 // columns); words: gang_words_bytes(nwg, S) bytes of exchange memory.
@@ -75,28 +79,59 @@ constexpr int32_t kMethodGroup = 2;
 
 // Exchange memory of a gang of nwg workgroups with slices of S columns, one
 // block: 2 * nwg stamped records (Pub, 32 bytes), the tagged records (32 bytes
-// per member and slot, see rec_word), then 2 * nwg * S 64-bit list words
-// (tagged bucket entries of the Dijkstra rounds, or the label-correcting
-// frontier).  Both kinds of record and the lists are double-buffered by
-// exchange parity.
+// per member and slot, see rec_word), the pair words (16 bytes per member: two
+// chunk-claim counters and a tagged "done" word, see solve_gang), then
+// 2 * nwg * S 64-bit list words (tagged bucket entries of the Dijkstra rounds,
+// or the label-correcting frontier).  Records and lists are double-buffered by
+// exchange parity.  The whole-GPU layout (grid_words) adds nwg * S 64-bit
+// partial keys (a pair partner's share of a member's columns).
 constexpr size_t kPubBytes = 32;
 constexpr size_t kTRecBytes = 32;
+constexpr size_t kPairBytes = 16;
 __host__ __device__ constexpr size_t gang_recs_offset(int nwg) { return 2 * (size_t)nwg * kPubBytes; }
-__host__ __device__ constexpr size_t gang_lists_offset(int nwg) {
+__host__ __device__ constexpr size_t gang_pair_offset(int nwg) {
     return gang_recs_offset(nwg) + 2 * (size_t)nwg * kTRecBytes;
 }
-__host__ __device__ constexpr size_t gang_words_bytes(int nwg, int S) {
+__host__ __device__ constexpr size_t gang_lists_offset(int nwg) {
+    return gang_pair_offset(nwg) + (size_t)nwg * kPairBytes;
+}
+__host__ __device__ constexpr size_t gang_part_offset(int nwg, int S) {
     return gang_lists_offset(nwg) + 2 * (size_t)nwg * (size_t)S * sizeof(uint64_t);
 }
+__host__ __device__ constexpr size_t gang_words_bytes(int nwg, int S) { return gang_part_offset(nwg, S); }
 
 struct GangWords {
     Pub* pubs;
     uint64_t* recs;
+    uint32_t* ctr;    // member g: ctr[4 g + slot], slot 0 or 1
+    uint64_t* done;   // member g: done[2 g] (the odd words are unused)
     uint64_t* lists;
+    uint64_t* part;   // member g: part[g S + local column] (whole-GPU layout only, else null)
 };
-__host__ __device__ inline GangWords gang_words(char* base, int nwg) {
+__host__ __device__ inline GangWords gang_words(char* base, int nwg, int S) {
     return GangWords{reinterpret_cast<Pub*>(base), reinterpret_cast<uint64_t*>(base + gang_recs_offset(nwg)),
-                     reinterpret_cast<uint64_t*>(base + gang_lists_offset(nwg))};
+                     reinterpret_cast<uint32_t*>(base + gang_pair_offset(nwg)),
+                     reinterpret_cast<uint64_t*>(base + gang_pair_offset(nwg)) + 1,
+                     reinterpret_cast<uint64_t*>(base + gang_lists_offset(nwg)), nullptr};
+}
+
+// The whole-GPU kernels' exchange memory (per-stream scratch, reused by
+// launches of every width): the stamped records always take the first
+// kGridPubBytes (room for 1024 members), so that stamps sit at the same
+// addresses in every use and no other word (the partial keys of pair
+// balancing can have bit 63 set) is ever left where a later launch polls a
+// stamp.  The rest follows as in gang_words.
+constexpr size_t kGridPubBytes = 2 * 1024 * kPubBytes;
+__host__ __device__ constexpr size_t grid_words_bytes(int nwg, int S) {
+    return kGridPubBytes + gang_words_bytes(nwg, S) - gang_recs_offset(nwg) +
+           (size_t)nwg * (size_t)S * sizeof(uint64_t);
+}
+__host__ __device__ inline GangWords grid_words(char* base, int nwg, int S) {
+    char* rest = base + kGridPubBytes - gang_recs_offset(nwg);  // the gang layout past its stamped records
+    GangWords gw = gang_words(rest, nwg, S);
+    gw.pubs = reinterpret_cast<Pub*>(base);
+    gw.part = reinterpret_cast<uint64_t*>(rest + gang_part_offset(nwg, S));
+    return gw;
 }
 
 // Arena bytes of an item's exchange memory (0 for a Dijkstra item solved by

@@ -47,7 +47,7 @@ class sssp_tuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("workgroups", ctypes.c_int32),
                 ("single_max_n", ctypes.c_int32), ("gang_columns", ctypes.c_int32),
                 ("group_sources", ctypes.c_int32), ("group_columns", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("balance", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class sssp_plan_info(ctypes.Structure):
@@ -204,13 +204,15 @@ def _ptr(t, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _tuning(threads=0, workgroups=0, single_max_n=0, gang_columns=0, group_sources=0, group_columns=0):
-    if not (threads or workgroups or single_max_n or gang_columns or group_sources or group_columns):
+def _tuning(threads=0, workgroups=0, single_max_n=0, gang_columns=0, group_sources=0, group_columns=0,
+            balance=0):
+    if not (threads or workgroups or single_max_n or gang_columns or group_sources or group_columns or balance):
         return None
     t = sssp_tuning()
     t.threads, t.workgroups = threads, workgroups
     t.single_max_n, t.gang_columns = single_max_n, gang_columns
     t.group_sources, t.group_columns = group_sources, group_columns
+    t.balance = balance
     return ctypes.byref(t)
 
 
@@ -222,7 +224,7 @@ def sssp_dense_solve(W, n, src, dist, pred, stream=None):
                                          _ptr(pred, "pred"), _stream(stream)))
 
 
-def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroups=0, stream=None):
+def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroups=0, stream=None, balance=0):
     """sssp_dense_solve_ex: W is an int32 device tensor holding n rows of stride ld."""
     # W may be a row-strided view (e.g. big[:, :n]): check the storage behind it
     avail = W.untyped_storage().nbytes() // 4 - W.storage_offset()
@@ -230,7 +232,7 @@ def sssp_dense_solve_ex(W, ld, n, src, dist, pred, flags=0, threads=0, workgroup
         raise ValueError("W is too small for n rows of stride ld, or its rows are not contiguous")
     return _check(lib().sssp_dense_solve_ex(_ptr(W, "W"), ld, n, src, _ptr(dist, "dist"),
                                             _ptr(pred, "pred"), flags,
-                                            _tuning(threads, workgroups), _stream(stream)))
+                                            _tuning(threads, workgroups, balance=balance), _stream(stream)))
 
 
 SSSP_NOALLOC_SCRATCH_BYTES = 8 << 20
@@ -452,12 +454,12 @@ def paths(pred, dist, targets):
 
 # ---- convenience wrappers (allocate outputs, return tensors) ----
 
-def solve(W, src, flags=0, threads=0, workgroups=0, stream=None):
+def solve(W, src, flags=0, threads=0, workgroups=0, stream=None, balance=0):
     """Solve from `src` on the int32 [n, ld] device tensor W; returns (dist, pred) tensors."""
     n = W.shape[0]
     dist = torch.empty(n, dtype=torch.int32, device=W.device)
     pred = torch.empty(n, dtype=torch.int32, device=W.device)
-    sssp_dense_solve_ex(W, W.stride(0), n, src, dist, pred, flags, threads, workgroups, stream)
+    sssp_dense_solve_ex(W, W.stride(0), n, src, dist, pred, flags, threads, workgroups, stream, balance)
     return dist, pred
 
 

@@ -5,7 +5,10 @@
 // use of that memory stores may equal a stamp: this program checks, over the
 // boundary values and random samples of every field, that stamps have bit 63
 // set while list entries, tagged words and records' other words at stamp
-// offsets do not, and that tagged words carry their tag.
+// offsets do not, and that tagged words carry their tag.  The partial keys of
+// pair balancing can have bit 63 set (a negative weight); they are written only
+// into the whole-GPU kernels' memory, whose stamp region is fixed (grid_words),
+// so they never sit where a later launch polls a stamp.
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
@@ -79,14 +82,32 @@ int main() {
     for (int i = 0; i < 100000; ++i) {
         const int32_t method = (int32_t)(rng() % 3), parts = 1 + (int32_t)(rng() % 1024),
                       S = 4 * (1 + (int32_t)(rng() % 4096));
-        CHECK(gang_recs_offset(parts) % 32 == 0 && gang_lists_offset(parts) % 32 == 0);
+        CHECK(gang_recs_offset(parts) % 32 == 0 && gang_lists_offset(parts) % 8 == 0);
         CHECK(gang_recs_offset(parts) == 2 * (size_t)parts * sizeof(Pub));
-        CHECK(gang_lists_offset(parts) == gang_recs_offset(parts) + 2 * (size_t)parts * kTRecBytes);
+        CHECK(gang_pair_offset(parts) == gang_recs_offset(parts) + 2 * (size_t)parts * kTRecBytes);
+        CHECK(gang_lists_offset(parts) == gang_pair_offset(parts) + (size_t)parts * kPairBytes);
+        CHECK(gang_pair_offset(parts) % 16 == 0 && gang_part_offset(parts, S) % 8 == 0);
+        // whole-GPU layout: stamps at fixed addresses below kGridPubBytes, nothing else there
+        const GangWords gg = grid_words(nullptr, parts, S);
+        CHECK((char*)gg.pubs == nullptr && (size_t)((char*)gg.recs - (char*)nullptr) == kGridPubBytes);
+        CHECK(grid_words_bytes(parts, S) ==
+              kGridPubBytes + gang_words_bytes(parts, S) - gang_recs_offset(parts) + 8 * (size_t)parts * (size_t)S);
+        CHECK((size_t)((char*)gg.lists - (char*)nullptr) + 16 * (size_t)parts * (size_t)S ==
+              (size_t)((char*)gg.part - (char*)nullptr));
+        CHECK((size_t)((char*)&gg.part[(size_t)parts * S - 1] - (char*)nullptr) + 8 == grid_words_bytes(parts, S));
         // the tagged words of every (slot, field, member) lie inside the tagged-record region
         uint64_t* recs = reinterpret_cast<uint64_t*>(gang_recs_offset(parts));
         const size_t last = (size_t)(rec_word(recs, parts, 1, kRecFields - 1, parts - 1) - recs);
         CHECK(last == 2 * (size_t)parts * kRecFields - 1);
-        CHECK(gang_words_bytes(parts, S) == gang_lists_offset(parts) + 16 * (size_t)parts * (size_t)S);
+        CHECK(gang_part_offset(parts, S) == gang_lists_offset(parts) + 16 * (size_t)parts * (size_t)S);
+        CHECK(gang_words_bytes(parts, S) == gang_part_offset(parts, S));
+        // the pair words: member g's two counters and its done word inside its 16 bytes
+        char* base = nullptr;
+        const GangWords gw = gang_words(base, parts, S);
+        const size_t g = (size_t)(parts - 1);
+        CHECK((size_t)((char*)&gw.ctr[4 * g + 1] - base) + 4 <= gang_pair_offset(parts) + 16 * g + 8);
+        CHECK((size_t)((char*)&gw.done[2 * g] - base) == gang_pair_offset(parts) + 16 * g + 8);
+        CHECK(gw.part == nullptr);
         if (method != kMethodGroup) {
             const unsigned long long bytes = item_scratch_bytes(method, parts, S);
             CHECK(bytes % 256 == 0);

@@ -33,10 +33,10 @@ def sp():
     sssp._lib = prev
 
 
-def check_dense(sp, W, src, flags=0, workgroups=0, Wt=None, tag=""):
+def check_dense(sp, W, src, flags=0, workgroups=0, Wt=None, tag="", balance=0):
     if Wt is None:
         Wt = torch.from_numpy(np.ascontiguousarray(W)).cuda()
-    d, p = sp.solve(Wt, src, flags=flags, workgroups=workgroups)
+    d, p = sp.solve(Wt, src, flags=flags, workgroups=workgroups, balance=balance)
     status, stats = sp.sssp_last_status()
     dr, pr, _ = oracle.dijkstra(W, src)
     assert status & 3 == 0, (tag, status)
@@ -79,6 +79,18 @@ def test_whole_gpu_rounds(sp):
         Wt = torch.from_numpy(W).cuda()
         for wg in (0, 3, 17, 64):
             check_dense(sp, W, int(rng.integers(0, n)), GRID, wg, Wt, ("grid", n, wg))
+
+
+def test_whole_gpu_balanced_rounds(sp):
+    """Rounds of ~8700 vertices (9 chunks): pair members claim each other's chunks,
+    and the pauses before claiming make partners steal."""
+    rng = np.random.default_rng(1303)
+    W = random_dense(rng, 9000, 0.97, 1, 1)
+    Wt = torch.from_numpy(W).cuda()
+    for wg in (0, 64, 17):
+        check_dense(sp, W, int(rng.integers(0, 9000)), GRID, wg, Wt, ("balanced", wg), balance=1)
+    Z = random_dense(rng, 9000, 0.95, 0, 1, zero_prob=0.2)
+    check_dense(sp, Z, 3, GRID, 0, tag="balanced-zero", balance=1)
 
 
 def test_whole_gpu_literal_and_zero_fallback(sp):
