@@ -236,15 +236,20 @@ __device__ __forceinline__ uint32_t lc_records(const Pub* rp, int nwg, SharedSol
         if (threadIdx.x < kWave) {
             const int q = (nwg + kWave - 1) / kWave;
             const int i0 = (int)threadIdx.x * q;
-            uint32_t cnt[4];
+            uint32_t cnt[4], fl[4];
             uint32_t f = 0, local = 0;
+            // all loads issued before any is used (record indexes clamped to the
+            // last member): a load per branch would be waited for before the next
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                cnt[k] = 0;
-                if (k < q && i0 + k < nwg) {
-                    cnt[k] = ld_agent(&rp[i0 + k].count);
-                    f |= ld_agent(&rp[i0 + k].flags);
-                }
+                const int m = min(i0 + k, nwg - 1);
+                cnt[k] = ld_agent(&rp[m].count);
+                fl[k] = ld_agent(&rp[m].flags);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!(k < q && i0 + k < nwg)) cnt[k] = fl[k] = 0;
+                f |= fl[k];
                 local += cnt[k];
             }
             f = wave_or32(f);

@@ -244,17 +244,22 @@ __device__ __forceinline__ bool solve_multi(const E* __restrict__ W, int64_t ld,
         uint32_t q = 0, len = 0;
         if ((int)threadIdx.x < nwg) {
             const uint64_t* r = rec(slot, threadIdx.x);
+            // the count words and the list length loaded together (a load per
+            // qualifying source would be waited for before the next)
+            uint64_t cwv[kMultiMax / 2];
+#pragma unroll
+            for (int k2 = 0; k2 < kMultiMax / 2; ++k2) cwv[k2] = 2 * k2 < K ? ld_agent(&r[2 + K + k2]) : 0ull;
+            const uint32_t lenv = (uint32_t)ld_agent(&r[1]);
             uint32_t settled = 0;
 #pragma unroll
             for (int k = 0; k < kMultiMax; ++k)
                 if (k < K && mk[k] != kRecNone && (uint32_t)(mk[k] >> 32) == (uint32_t)(mh.gkey[k] >> 32) &&
                     (uint32_t)(mh.gkey[k] >> 32) < kInf) {
                     q |= 1u << k;
-                    const uint64_t cw = ld_agent(&r[2 + K + k / 2]);
-                    settled += (uint32_t)(k & 1 ? cw >> 32 : cw);
+                    settled += (uint32_t)(k & 1 ? cwv[k / 2] >> 32 : cwv[k / 2]);
                 }
             if (q) {
-                len = (uint32_t)ld_agent(&r[1]);
+                len = lenv;
                 __hip_atomic_fetch_add(&mh.settled, settled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             mh.qual[threadIdx.x] = q;
