@@ -1,6 +1,6 @@
 // Diagnostic: the read bandwidth this device delivers to a plain streaming
 // kernel, the practical ceiling against which the row-streaming solves are
-// judged (the published HBM peak is not reachable by reads alone).
+// measured (the published HBM peak is not reachable by reads alone).
 //
 // Workgroups claim fixed-size chunks from a counter until none is left, so
 // faster XCDs read more chunks than slower ones: a static split (every

@@ -43,7 +43,7 @@ def check(sp, W, src, workgroups, tag):
 
 def test_rounds_of_most_vertices(sp):
     rng = np.random.default_rng(3100)
-    W = random_dense(rng, 9000, 0.97, 1, 1)  # round 2 holds ~8700 vertices (9 chunks)
+    W = random_dense(rng, 9000, 0.97, 1, 1)  # the solve's second round holds ~8700 vertices (9 chunks)
     for wg in (0, 64, 7, 255):
         stats = check(sp, W, int(rng.integers(0, 9000)), wg, ("unit", wg))
         assert stats[0] <= 4
