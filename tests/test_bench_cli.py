@@ -37,3 +37,19 @@ def test_source_hash_ignores_comments_only():
     assert code_tokens(base) == code_tokens(comment_edit)
     assert code_tokens(base) != code_tokens(code_edit)
     assert code_tokens(base) != code_tokens(literal_edit)
+
+
+def test_committed_counters_match_the_kernel_sources():
+    """The committed n=65536 counter summary was taken with the current kernel
+    code: bench.py then reports its HBM traffic (roofline.traffic) instead of
+    null, and the traffic is the algorithmic bytes within a few percent."""
+    sys.path.insert(0, ROOT)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    traffic = bench.read_traffic("k_grid_n65536_counters.txt")
+    assert traffic is not None, "profiles/k_grid_n65536_counters.txt is stale: re-profile the n=65536 solve"
+    n = 65536
+    algorithmic = 4 * n * n + 8 * n  # every row relaxed once, dist and pred written once
+    assert 1.0 <= traffic / algorithmic < 1.05
