@@ -421,7 +421,14 @@ typedef struct sssp_server_config {
     int32_t idle_wait_us;   /* with nothing pending or in flight, the server thread beats the heartbeat
                                and looks for work this often (0 = 1000); above watchdog_ms the kernel
                                leaves whenever the server is idle and is relaunched on the next query */
-    int32_t reserved[2];
+    int32_t busy_gang_columns;  /* throughput mode: a Dijkstra gang query admitted with at least
+                                   busy_queue queries waiting behind it is split into slices of this
+                                   many columns (fewer members: less exchange cost per query, higher
+                                   throughput under a backlog); 0 = 2 x gang_columns for int32
+                                   graphs, 4 x for compact copies (at most 16384); < 0 = off;
+                                   otherwise a multiple of 4, at most 16384 */
+    int32_t busy_queue;     /* queries waiting behind a query that switch it to throughput mode
+                               (0 = 128) */
 } sssp_server_config;
 
 /* query states */
@@ -454,17 +461,19 @@ int64_t sssp_server_now_ns(void);
 /* The split the server gives an n-vertex query, computed on the host (no
  * device, no server): with configuration *cfg (NULL = all defaults; filled in as
  * sssp_server_create does) on a kernel of `workgroups` workgroups, for the
- * Dijkstra rounds (method 0) or the label-correcting method (1), when `busy`
- * workgroups already hold queries in flight and `waiting` queries are queued
- * behind it (the latency-mode split of idle_gang_columns applies only when
- * waiting == 0).  *parts: workgroups that solve it (1 = one workgroup);
- * *columns: columns per member (n for a Dijkstra query solved by one workgroup
- * alone; otherwise a multiple of 4, also for a label-correcting gang of one);
- * *scratch_bytes (may be NULL): arena bytes for its exchange records.
- * SSSP_ENOMEM if the query could never fit the arena (sssp_server_submit
- * refuses it the same way). */
-int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t busy,
-                      int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes);
+ * Dijkstra rounds (method 0) or the label-correcting method (1) on a graph
+ * stored with `elem` bytes per entry (4: the caller's int32 matrix; 2 / 1: a
+ * compact copy), when `busy` workgroups already hold queries in flight and
+ * `waiting` queries are queued behind it (the latency-mode split of
+ * idle_gang_columns applies when waiting == 0, the throughput-mode split of
+ * busy_gang_columns when waiting >= busy_queue).  *parts: workgroups that
+ * solve it (1 = one workgroup); *columns: columns per member (n for a
+ * Dijkstra query solved by one workgroup alone; otherwise a multiple of 4, also
+ * for a label-correcting gang of one); *scratch_bytes (may be NULL): arena
+ * bytes for its exchange records.  SSSP_ENOMEM if the query could never fit the
+ * arena (sssp_server_submit refuses it the same way). */
+int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t elem,
+                      int32_t busy, int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes);
 
 /* Creates a server on the current device and launches its kernel; cfg may be NULL. */
 int sssp_server_create(const sssp_server_config* cfg, sssp_server** out);

@@ -121,7 +121,7 @@ struct Arena {
 
 // Host policy of the server, free of any device state (so that it can be
 // queried and tested without a GPU): configuration defaults, the gang shape of
-// a query, and the latency-mode split at admission.
+// a query, and the latency-mode and throughput-mode splits at admission.
 namespace {
 
 int normalize(sssp_server_config& c) {
@@ -138,6 +138,9 @@ int normalize(sssp_server_config& c) {
     c.lc_gang_columns = (c.lc_gang_columns + 3) & ~3;
     if (c.idle_gang_columns == 0) c.idle_gang_columns = std::max(256, c.gang_columns / 4);
     if (c.idle_gang_columns > 0) c.idle_gang_columns = (c.idle_gang_columns + 3) & ~3;
+    if (c.busy_queue <= 0) c.busy_queue = 128;
+    if (c.busy_gang_columns > max_serve_slice() || (c.busy_gang_columns > 0 && c.busy_gang_columns % 4))
+        return err(SSSP_EINVAL, "busy_gang_columns <= %d (multiple of 4) required", max_serve_slice());
     if (c.single_max_n > max_serve_single_n() || c.gang_columns > max_serve_slice() || c.gang_columns % 4)
         return err(SSSP_EINVAL, "single_max_n <= %d and gang_columns <= %d (multiple of 4) required",
                    max_serve_single_n(), max_serve_slice());
@@ -191,6 +194,28 @@ void latency_split(const sssp_server_config& cfg, int nwg, int64_t busy, int32_t
         *parts = p2;
         *S = S2;
         *bytes = b2;
+    }
+}
+
+// Throughput mode: a Dijkstra gang query admitted with at least busy_queue
+// queries waiting behind it is split into wider slices (fewer members).  Under
+// a backlog the workgroup time per query, not the query's latency, sets the
+// throughput, and wider slices cut the per-member cost of every round (the
+// exchange and the spread of finish times).  Default width: twice gang_columns
+// for the caller's int32 matrices, four times for compact copies (the widths
+// that served the most queries per second on the served workload).  Updates
+// parts / S / bytes when it widens the split.
+void throughput_split(const sssp_server_config& cfg, int nwg, int32_t n, int32_t method, int32_t elem,
+                      int32_t* parts, int32_t* S, uint64_t* bytes) {
+    if (*parts <= 1 || method != kMethodDijkstra || cfg.busy_gang_columns < 0) return;
+    int64_t cols = cfg.busy_gang_columns > 0 ? cfg.busy_gang_columns : (int64_t)cfg.gang_columns * (elem < 4 ? 4 : 2);
+    cols = std::min<int64_t>(cols, max_serve_slice()) & ~int64_t(3);
+    int32_t p2 = 0, S2 = 0;
+    gang_shape(cfg, nwg, n, method, &p2, &S2, (int32_t)cols);
+    if (p2 < *parts) {
+        *parts = p2;
+        *S = S2;
+        *bytes = footprint(method, p2, S2);
     }
 }
 
@@ -284,6 +309,10 @@ struct sssp_server {
             if (!q.replanned && pending.size() == 1) {
                 q.replanned = true;
                 latency_split(cfg, nwg, ring_used, graphs[q.graph].n, q.method, &q.parts, &q.S, &q.bytes);
+            } else if (!q.replanned && (int64_t)pending.size() - 1 >= cfg.busy_queue) {
+                q.replanned = true;
+                throughput_split(cfg, nwg, graphs[q.graph].n, q.method, graphs[q.graph].elem, &q.parts, &q.S,
+                                 &q.bytes);
             }
             if (ring_used + q.parts > cfg.ring_slots) break;
             uint64_t off = 0;
@@ -458,12 +487,12 @@ extern "C" {
 
 int64_t sssp_server_now_ns(void) { return now_ns(); }
 
-int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t busy,
-                      int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes) {
+int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t n, int32_t method, int32_t elem,
+                      int32_t busy, int32_t waiting, int32_t* parts, int32_t* columns, int64_t* scratch_bytes) {
     if (!parts || !columns || workgroups < 1 || n < 1 || (method != kMethodDijkstra && method != kMethodLabelCorrecting) ||
-        busy < 0 || waiting < 0)
-        return err(SSSP_EINVAL, "bad arguments (workgroups=%d n=%d method=%d busy=%d waiting=%d)", workgroups, n,
-                   method, busy, waiting);
+        (elem != 1 && elem != 2 && elem != 4) || busy < 0 || waiting < 0)
+        return err(SSSP_EINVAL, "bad arguments (workgroups=%d n=%d method=%d elem=%d busy=%d waiting=%d)", workgroups,
+                   n, method, elem, busy, waiting);
     sssp_server_config c{};
     if (cfg) c = *cfg;
     if (int rc = normalize(c)) return rc;
@@ -474,6 +503,7 @@ int sssp_server_shape(const sssp_server_config* cfg, int32_t workgroups, int32_t
         return err(SSSP_ENOMEM, "query needs %llu scratch bytes, arena has %lld", (unsigned long long)bytes,
                    (long long)c.scratch_bytes);
     if (waiting == 0) latency_split(c, workgroups, busy, n, method, &p, &S, &bytes);
+    else if (waiting >= c.busy_queue) throughput_split(c, workgroups, n, method, elem, &p, &S, &bytes);
     *parts = p;
     *columns = S;
     if (scratch_bytes) *scratch_bytes = (int64_t)bytes;

@@ -80,7 +80,7 @@ class sssp_server_config(ctypes.Structure):
                 ("idle_park_ms", ctypes.c_int32), ("lc_rounds", ctypes.c_int32),
                 ("lc_gang_columns", ctypes.c_int32), ("lc_model", ctypes.c_int32),
                 ("idle_gang_columns", ctypes.c_int32), ("idle_wait_us", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("busy_gang_columns", ctypes.c_int32), ("busy_queue", ctypes.c_int32)]
 
 
 class sssp_query_info(ctypes.Structure):
@@ -168,7 +168,7 @@ def _declare(L):
     L.sssp_csr_grid.argtypes = [I32, ctypes.POINTER(sssp_tuning), P, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                 ctypes.POINTER(I32)]
     L.sssp_server_now_ns.restype = I64
-    L.sssp_server_shape.argtypes = [ctypes.POINTER(sssp_server_config), I32, I32, I32, I32, I32,
+    L.sssp_server_shape.argtypes = [ctypes.POINTER(sssp_server_config), I32, I32, I32, I32, I32, I32,
                                     ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I64)]
     L.sssp_server_create.argtypes = [ctypes.POINTER(sssp_server_config), ctypes.POINTER(P)]
     L.sssp_server_add_graph.argtypes = [P, P, I64, I32, ctypes.POINTER(I32)]
@@ -529,8 +529,9 @@ def sssp_server_now_ns():
     return lib().sssp_server_now_ns()
 
 
-def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, **cfg):
-    """sssp_server_shape (host only): (parts, columns, scratch_bytes) of an n-vertex query."""
+def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, elem=4, **cfg):
+    """sssp_server_shape (host only): (parts, columns, scratch_bytes) of an n-vertex query
+    on a graph stored with `elem` bytes per entry."""
     c = sssp_server_config()
     names = {f for f, _ in sssp_server_config._fields_} - {"reserved"}
     for k, v in cfg.items():
@@ -538,7 +539,7 @@ def sssp_server_shape(workgroups, n, method=0, busy=0, waiting=0, **cfg):
             raise TypeError("unknown server setting %r" % k)
         setattr(c, k, v)
     parts, cols, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
-    _check(lib().sssp_server_shape(ctypes.byref(c), workgroups, n, method, busy, waiting, ctypes.byref(parts),
+    _check(lib().sssp_server_shape(ctypes.byref(c), workgroups, n, method, elem, busy, waiting, ctypes.byref(parts),
                                    ctypes.byref(cols), ctypes.byref(b)))
     return parts.value, cols.value, b.value
 

@@ -228,3 +228,34 @@ def test_server_latency_mode_gangs(sp):
         t = srv.submit(gid, 3, d, p)
         srv.wait(t, timeout_s=60)
         assert srv.info(t)["parts"] == 3
+
+
+def test_server_throughput_mode_gangs(sp):
+    """A gang query admitted with at least busy_queue queries waiting behind it is
+    split into wider slices (busy_gang_columns; by default twice gang_columns for
+    int32 graphs and four times for compact copies); the queries near the end of
+    the burst keep the ordinary split.  Results are the oracle's either way."""
+    rng = np.random.default_rng(206)
+    graphs = make_graphs(rng, [5000, 9000])
+    dev = [torch.from_numpy(W).cuda() for W in graphs]
+    refs = {}
+    for flags in (0, sp.SSSP_FLAG_COMPACT):
+        # four queries in flight at most, so that the burst waits for admission
+        with sp.Server(single_max_n=1024, gang_columns=1024, idle_gang_columns=-1, busy_queue=8, max_inflight=4,
+                       lc_rounds=-1) as srv:
+            gids = [srv.add_graph(W, flags) for W in dev]
+            outs = [outputs(graphs[k % 2].shape[0]) for k in range(48)]
+            ts = [srv.submit(gids[k % 2], 3 + k, *outs[k]) for k in range(48)]
+            parts = {0: set(), 1: set()}
+            for k, t in enumerate(ts):
+                srv.wait(t, timeout_s=60)
+                parts[k % 2].add(srv.info(t)["parts"])
+                if (k, 3 + k) not in refs:
+                    refs[(k, 3 + k)] = oracle.dijkstra(graphs[k % 2], 3 + k)
+                dr, pr, _ = refs[(k, 3 + k)]
+                assert np.array_equal(outs[k][0].cpu().numpy(), dr) and np.array_equal(outs[k][1].cpu().numpy(), pr)
+            elem = srv.graph_elem(gids[1])
+            wide_cols = 1024 * (4 if elem < 4 else 2)
+            # n = 9000: 9 members in the ordinary split, ceil(9000 / wide_cols) under the backlog
+            assert -(-9000 // wide_cols) in parts[1] and 9 in parts[1], (flags, elem, parts)
+            assert -(-5000 // wide_cols) in parts[0] or 2 in parts[0], (flags, parts)

@@ -3,7 +3,8 @@ gives a query, without a device): one workgroup up to single_max_n; gangs of
 gang_columns (label-correcting: lc_gang_columns) per member, at least two
 members, at most half the kernel's workgroups; the latency-mode split (narrower
 slices when nothing waits, within three quarters of the workgroups minus those
-busy); arena bytes; argument errors."""
+busy); the throughput-mode split (wider slices under a backlog of busy_queue
+queries, by the graph's entry size); arena bytes; argument errors."""
 import pytest
 
 DIJ, LC = 0, 1
@@ -63,6 +64,39 @@ def test_latency_mode(sp):
     assert m.sssp_server_shape(248, 3000, waiting=0)[:2] == (1, 3000)
 
 
+def test_throughput_mode(sp):
+    m, sssp = sp
+    n = 30979
+    wide = m.sssp_server_shape(248, n, waiting=1)
+    assert wide[0] == ceil_div(n, 2048)
+    # a backlog of busy_queue (128) queries: twice the width for int32 graphs, four
+    # times for compact copies; below it, the ordinary wide split
+    assert m.sssp_server_shape(248, n, waiting=127)[:2] == wide[:2]
+    p4, c4, b4 = m.sssp_server_shape(248, n, waiting=128)
+    assert p4 == ceil_div(n, 4096) and b4 < wide[2]
+    check_split(n, p4, c4)
+    for elem in (1, 2):
+        pc, cc, _ = m.sssp_server_shape(248, n, waiting=500, elem=elem)
+        assert pc == ceil_div(n, 8192)
+        check_split(n, pc, cc)
+    # never fewer than two members, never wider than 16384 columns
+    assert m.sssp_server_shape(248, 9000, waiting=1000, elem=1)[0] == 2
+    assert m.sssp_server_shape(248, 65536, waiting=1000, elem=1)[:2] == (8, 8192)
+    assert m.sssp_server_shape(248, 65536, waiting=1000, elem=1, gang_columns=8192)[:2] == (4, 16384)
+    # set explicitly, or switched off; the threshold is configurable
+    assert m.sssp_server_shape(248, n, waiting=500, busy_gang_columns=3072)[0] == ceil_div(n, 3072)
+    assert m.sssp_server_shape(248, n, waiting=500, busy_gang_columns=-1)[:2] == wide[:2]
+    assert m.sssp_server_shape(248, n, waiting=10, busy_queue=10)[0] == ceil_div(n, 4096)
+    # label-correcting queries and single-workgroup queries keep their split
+    assert m.sssp_server_shape(248, 7323, method=LC, waiting=500)[:2] == m.sssp_server_shape(248, 7323, method=LC,
+                                                                                              waiting=1)[:2]
+    assert m.sssp_server_shape(248, 3000, waiting=500)[:2] == (1, 3000)
+    for kw in (dict(busy_gang_columns=6), dict(busy_gang_columns=16388), dict(elem=3)):
+        with pytest.raises(sssp.SsspError) as x:
+            m.sssp_server_shape(248, n, waiting=500, **kw)
+        assert x.value.code == sssp.SSSP_EINVAL
+
+
 def test_label_correcting_gangs(sp):
     m, _ = sp
     # label-correcting: a gang even below single_max_n (possibly of one), lc_gang_columns wide
@@ -120,7 +154,11 @@ def test_random_shapes_obey_the_contract(sp):
         cfg = dict(single_max_n=single, gang_columns=gang, lc_gang_columns=lc_gang, idle_gang_columns=idle)
         wide = m.sssp_server_shape(W, n, method=method, busy=busy, waiting=1, **cfg)
         lat = m.sssp_server_shape(W, n, method=method, busy=busy, waiting=0, **cfg)
-        for parts, cols, b in (wide, lat):
+        elem = int(rng.choice([1, 2, 4]))
+        busy_cols = int(rng.choice([0, -1, 4096]))
+        thr = m.sssp_server_shape(W, n, method=method, busy=busy, waiting=200, elem=elem, busy_gang_columns=busy_cols,
+                                  **cfg)
+        for parts, cols, b in (wide, lat, thr):
             assert parts >= 1 and b % 256 == 0, (trial, parts, cols, b)
             if parts == 1 and method == 0:
                 assert cols == n
@@ -144,3 +182,9 @@ def test_random_shapes_obey_the_contract(sp):
             assert idle > 0 and lat[0] <= -(-n // idle), (trial, idle, n, lat)
         if idle < 0:
             assert lat[:2] == wide[:2]
+        # the throughput split: never more members than the wide one, at least two
+        assert thr[0] <= wide[0], (trial, wide, thr)
+        if method == 0:
+            assert thr[0] >= 2
+        if method == 1 or busy_cols < 0:
+            assert thr[:2] == wide[:2]
