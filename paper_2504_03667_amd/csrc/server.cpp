@@ -9,7 +9,9 @@
 // while others run are admitted as slots and memory free up and run
 // concurrently on the GPU.  A host thread admits, collects completion records
 // written by the GPU into pinned memory, timestamps them, and keeps a
-// heartbeat that the kernel watches so it leaves if the host goes away.
+// heartbeat that the kernel watches so it leaves if the host goes away.  A
+// gang query's split follows the queue: narrower slices when nothing waits
+// behind it (latency), wider ones behind a backlog (throughput).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
